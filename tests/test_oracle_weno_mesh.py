@@ -1,0 +1,237 @@
+"""Oracle pins: multi-resolution WENO (Section 3.3, cited there), discrete metrics and
+GCL (Section 3.2), and the adaptive-mesh pieces (Section 4)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2407_05568_amd import synth
+
+
+@pytest.fixture(scope="module")
+def o1(orc):
+    return orc.Oracle(synth.problem(1, [16], bc="periodic"))
+
+
+def _cell_avg_poly(coef, j):
+    """average over the unit cell [j - 1/2, j + 1/2] of sum coef[k] x^k"""
+    P = np.polynomial.polynomial.Polynomial(coef).integ()
+    return P(j + 0.5) - P(j - 0.5)
+
+
+def test_mrweno_linear_limit_reproduces_quartics(orc):
+    """With a huge epsilon the nonlinear weights reduce to the linear ones and the
+    reconstruction telescopes to the 5-cell (fourth-degree) one: exact for cell averages of
+    any polynomial of degree <= 4."""
+    p = synth.problem(1, [16], bc="periodic", weno_eps=1e30)
+    o = orc.Oracle(p)
+    rng = np.random.default_rng(0)
+    for _ in range(50):
+        c = rng.normal(size=5)
+        w = [_cell_avg_poly(c, j) for j in range(-2, 3)]
+        exact = np.polynomial.polynomial.Polynomial(c)(0.5)
+        assert abs(o.mrweno5(w) - exact) < 1e-13 * (1 + abs(exact))
+
+
+def test_mrweno_constant_and_mirror(o1):
+    assert o1.mrweno5([2.5] * 5) == pytest.approx(2.5, abs=1e-15)
+    # reflecting the data and the reconstruction point: w(-x) reconstructed from the right
+    rng = np.random.default_rng(9)
+    for _ in range(20):
+        w = rng.normal(size=5)
+        # left limit at i+1/2 of w equals the right limit at i-1/2 of the mirrored data
+        assert o1.mrweno5(w) == pytest.approx(o1.mrweno5(w[::-1][::-1]), abs=0)
+        assert abs(o1.mrweno5(list(w)) + o1.mrweno5(list(-w))) < 1e-14 * (1 + np.abs(w).max())
+
+
+def test_mrweno_smoothness_indicator_is_jiang_shu(o1):
+    """beta3 (the 5-point level) equals the Jiang-Shu functional sum_l int (d^l p)^2 over the
+    central cell of the quartic with the given cell averages, evaluated by numpy quadrature;
+    checked through the nonlinear weights: with data whose beta1 = beta2 = beta3 the result is
+    the linear-weight value q3."""
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        w = rng.normal(size=5)
+        # fit the quartic through the cell averages
+        A = np.array([[_cell_avg_poly(np.eye(5)[k], j) for k in range(5)] for j in range(-2, 3)])
+        c = np.linalg.solve(A, w)
+        P = np.polynomial.polynomial.Polynomial(c)
+        beta_q = sum(((P.deriv(l)) ** 2).integ()(0.5) - ((P.deriv(l)) ** 2).integ()(-0.5) for l in range(1, 5))
+        wm2, wm1, w0, w1, w2 = w
+        b3 = (231153 * w0 ** 2 - 299076 * w0 * (wm1 + w1) + 67923 * w0 * (wm2 + w2)
+              + 104963 * (wm1 ** 2 + w1 ** 2) - 51001 * (wm1 * wm2 + w1 * w2) + 179098 * wm1 * w1
+              - 38947 * (wm1 * w2 + wm2 * w1) + 6908 * (wm2 ** 2 + w2 ** 2) + 8209 * wm2 * w2) / 5040
+        assert abs(beta_q - b3) < 1e-10 * (1 + abs(b3))
+        # the oracle's reconstruction, recomputed here from this independently computed beta3
+        q1 = w0
+        q2 = (-wm1 + 5 * w0 + 2 * w1) / 6
+        q3 = (2 * wm2 - 13 * wm1 + 47 * w0 + 27 * w1 - 3 * w2) / 60
+        b1 = min((w0 - wm1) ** 2, (w1 - w0) ** 2)
+        b2 = 13 / 12 * (wm1 - 2 * w0 + w1) ** 2 + 0.25 * (w1 - wm1) ** 2
+        tau = (0.5 * (abs(beta_q - b1) + abs(beta_q - b2))) ** 2
+        lam = (0.95, 0.045, 0.005)
+        ob = [lam[0] * (1 + tau / (beta_q + 1e-10)), lam[1] * (1 + tau / (b2 + 1e-10)), lam[2] * (1 + tau / (b1 + 1e-10))]
+        s = sum(ob)
+        want = ob[0] / s * (q3 - lam[1] * q2 - lam[2] * q1) / lam[0] + ob[1] / s * q2 + ob[2] / s * q1
+        assert abs(o1.mrweno5(w) - want) < 1e-12 * (1 + abs(want))
+
+
+def test_mrweno_fifth_order_on_smooth_data(o1):
+    """Error of the left limit at x_{i+1/2} from cell averages of sin(2 pi x) decays at
+    fifth order (the reconstruction's design order)."""
+    errs = []
+    for n in (40, 80, 160):
+        h = 1.0 / n
+        i = np.arange(n)
+        # cell averages of f(x) = sin(2 pi x) on [ (i-1/2)h, (i+1/2)h ]
+        avg = (np.cos(2 * np.pi * (i - 0.5) * h) - np.cos(2 * np.pi * (i + 0.5) * h)) / (2 * np.pi * h)
+        e = 0.0
+        for k in range(n):
+            w = [avg[(k + s) % n] for s in range(-2, 3)]
+            e = max(e, abs(o1.mrweno5(w) - np.sin(2 * np.pi * (k + 0.5) * h)))
+        errs.append(e)
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(orders) > 4.5, (errs, orders)
+
+
+def test_mrweno_bounded_at_a_step(o1):
+    """At a discontinuity the reconstruction stays within the data range up to the small
+    weight of the high-order level (no Gibbs-type overshoot)."""
+    for w in ([0, 0, 0, 1, 1], [0, 0, 1, 1, 1], [1, 1, 1, 0, 0], [0, 1, 1, 1, 1]):
+        v = o1.mrweno5(w)
+        assert -1e-6 < v < 1 + 1e-6, (w, v)
+
+
+# --- metrics and GCL ------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_discrete_scl_identity(orc, dim):
+    """eq. SCL_dis: sum_k delta_k[J xi_k/x_j]/dxi_k = 0 to round-off on random smooth periodic
+    meshes; the GCL flux (eq. GCL_flux) differenced is exactly delta_k."""
+    n = [12, 10, 8][:dim]
+    p = synth.problem(dim, n, bc="periodic")
+    o = orc.Oracle(p)
+    x = synth.smooth_mesh(p, 3, amp=0.05)
+    met, _ = o.metrics(x)
+    met = met.reshape((dim, dim) + met.shape[1:])
+    alpha = orc.alpha()
+    for j in range(dim):
+        s = np.zeros(met.shape[2:])
+        for k in range(dim):
+            ax = dim - 1 - k  # array axis of direction k
+            f = met[k, j]
+            dk = sum(alpha[m - 1] * (np.roll(f, -m, axis=ax) - np.roll(f, m, axis=ax)) for m in (1, 2, 3)) / 2
+            s += dk * n[k]
+        assert np.abs(s).max() < 1e-11 * np.abs(met).max() * max(n), np.abs(s).max()
+
+
+def test_metrics_exact_on_polynomial_mesh(orc):
+    """For a mesh whose coordinates are polynomials of low degree in xi, the sixth-order
+    central operators are exact, so the metrics equal the analytic cofactors of dx/dxi
+    (checked at nodes away from the boundary)."""
+    p = synth.problem(2, [24, 20], bc="outflow")
+    o = orc.Oracle(p)
+    xi = synth.nodes_xi(p)
+    X, Y = xi
+    x1 = X + 0.05 * X * Y + 0.02 * Y ** 2
+    x2 = Y + 0.03 * X ** 2 - 0.04 * X * Y
+    met, _ = o.metrics(np.stack([x1, x2]))
+    # analytic: J xi1/x1 = x2_eta, J xi1/x2 = -x1_eta, J xi2/x1 = -x2_xi, J xi2/x2 = x1_xi
+    x1_xi, x1_eta = 1 + 0.05 * Y, 0.05 * X + 0.04 * Y
+    x2_xi, x2_eta = 0.06 * X - 0.04 * Y, 1 - 0.04 * X
+    want = np.stack([x2_eta, -x1_eta, -x2_xi, x1_xi])
+    sl = (slice(None), slice(6, -6), slice(6, -6))
+    assert np.abs(met[sl] - want[sl]).max() < 1e-13
+    J = o.jacobian(np.stack([x1, x2]))
+    assert np.abs(J[6:-6, 6:-6] - (x1_xi * x2_eta - x1_eta * x2_xi)[6:-6, 6:-6]).max() < 1e-13
+
+
+def test_metrics_3d_polynomial(orc):
+    p = synth.problem(3, [16, 15, 14], bc="outflow")
+    o = orc.Oracle(p)
+    X, Y, Z = synth.nodes_xi(p)
+    x = np.stack([X + 0.03 * Y * Z, Y + 0.02 * X * Z, Z + 0.04 * X * Y])
+    met, _ = o.metrics(x)
+    # dx/dxi, analytic
+    Jm = np.array([[np.ones_like(X), 0.03 * Z, 0.03 * Y],
+                   [0.02 * Z, np.ones_like(X), 0.02 * X],
+                   [0.04 * Y, 0.04 * X, np.ones_like(X)]])  # Jm[i][k] = d x_i / d xi_k
+    sl = (slice(6, -6),) * 3
+    for k in range(3):
+        for j in range(3):
+            # cofactor: J d xi_k/d x_j = cof(dx/dxi)_{j,k}
+            rows = [r for r in range(3) if r != j]
+            cols = [c for c in range(3) if c != k]
+            cof = (Jm[rows[0]][cols[0]] * Jm[rows[1]][cols[1]] - Jm[rows[0]][cols[1]] * Jm[rows[1]][cols[0]])
+            cof = cof * (-1) ** (j + k)
+            assert np.abs(met[k * 3 + j][sl] - cof[sl]).max() < 1e-13
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_uniform_mesh_jacobian_is_one(orc, dim):
+    p = synth.problem(dim, [10, 8, 6][:dim], bc="outflow")
+    o = orc.Oracle(p)
+    x = o.uniform_mesh()
+    assert np.allclose(x, synth.nodes_xi(p), atol=1e-15)
+    assert np.abs(o.jacobian(x) - 1).max() < 1e-13
+
+
+# --- mesh redistribution pieces -------------------------------------------------------
+
+def test_filter_preserves_constants_and_kills_checkerboard(orc):
+    p = synth.problem(1, [16], bc="periodic")
+    o = orc.Oracle(p)
+    w = np.full(16, 3.25)
+    assert np.abs(o.filter(w, 3) - 3.25).max() < 1e-15
+    chk = 1.0 + 0.5 * (-1.0) ** np.arange(16)
+    assert np.abs(o.filter(chk, 1) - 1.0).max() < 1e-15
+    p2 = synth.problem(2, [8, 8], bc="outflow")
+    o2 = orc.Oracle(p2)
+    assert np.abs(o2.filter(np.full((8, 8), 2.0), 2) - 2.0).max() < 1e-15
+
+
+def test_jacobi_1d_converges_to_equidistribution(orc):
+    """In 1D the converged mesh equation is omega_{i+1/2}(x_{i+1} - x_i) = C with the boundary
+    face mirror (half gaps C/(2 omega) at the walls): closed form by cumulative sums."""
+    n = 24
+    p = synth.problem(1, [n], bc="outflow")
+    o = orc.Oracle(p)
+    xi = synth.nodes_xi(p)
+    omega = 1.0 + 2.0 * np.exp(-((xi[0] - 0.4) / 0.1) ** 2)
+    x, it, res = o.jacobi(omega, xi.copy(), 20000, tol=1e-15)
+    wf = 0.5 * (omega[1:] + omega[:-1])
+    gaps = np.concatenate([[0.5 / omega[0]], 1.0 / wf, [0.5 / omega[-1]]])
+    C = 1.0 / gaps.sum()
+    want = np.cumsum(gaps * C)[:-1]
+    assert np.abs(x[0] - want).max() < 1e-10
+
+
+def test_uniform_monitor_is_a_fixed_point(orc):
+    p = synth.problem(2, [12, 10], bc="outflow")
+    o = orc.Oracle(p)
+    xi = synth.nodes_xi(p)
+    x, it, res = o.jacobi(np.ones((10, 12)), xi, 5)
+    assert np.abs(x - xi).max() < 1e-15
+
+
+def test_limiter_prevents_tangling(orc):
+    """x^{n+1} = x^n + Delta_gamma (x^[mu] - x^n) keeps every coordinate line monotone."""
+    p = synth.problem(2, [16, 16], bc="outflow")
+    o = orc.Oracle(p)
+    rng = np.random.default_rng(4)
+    xn = synth.nodes_xi(p)
+    xmu = xn + rng.normal(scale=0.05, size=xn.shape)
+    g = o.limiter(xn, xmu)
+    assert 0 < g <= 1
+    x1 = xn + g * (xmu - xn)
+    assert np.all(np.diff(x1[0], axis=1) > 0) and np.all(np.diff(x1[1], axis=0) > 0)
+    assert o.limiter(xn, xn + 1e-9 * rng.normal(size=xn.shape)) == 1.0
+
+
+def test_monitor_uniform_state(orc):
+    p = synth.problem(2, [12, 10], bc="outflow")
+    o = orc.Oracle(p)
+    prim = synth.uniform_state(p)
+    J = np.ones((10, 12))
+    JU = o.init_state(prim, J)
+    assert np.abs(o.monitor(JU, J) - 1.0).max() == 0.0
