@@ -1,0 +1,157 @@
+/*
+ * esvdw.h -- C ABI of the MI355X (gfx950) library for the high-order entropy-stable
+ * finite-difference scheme on adaptive moving meshes for the Euler equations with the
+ * van der Waals equation of state (S. Li, H. Tang, arXiv 2407.05568).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All arrays are DEVICE pointers to caller-owned, contiguous FP64 memory, laid out
+ *    field-major over the interior nodes: a[var][z][y][x], x fastest, no ghost layers.
+ *    N = n[0]*n[1]*n[2] (unused directions have n = 1); nv = dim + 2 conserved variables
+ *    (rho, rho v_1..v_dim, E).  Boundary conditions are applied inside the library.
+ *  - Nodes are cell-centred in the computational box: xi_i = lo + (i + 1/2) dxi,
+ *    dxi = (hi - lo)/n, matching the fixed uniform computational mesh of Section 3.
+ *  - Every call is asynchronous on the given stream, never synchronises the host and
+ *    allocates nothing (scratch belongs to the context); sequences of calls can be captured
+ *    into a HIP graph.  Device scalars (dt, residuals, sweep counts) go to caller device
+ *    pointers.
+ *  - The int return value reports synchronous errors only: ESVDW_OK, ESVDW_EINVAL (null
+ *    pointer, bad size or option), ESVDW_EHIP (a HIP launch failed).  Numerical conditions
+ *    found by the kernels (inadmissible states, failure of the mean-value constraint of
+ *    Theorem 3.1, NaN, mesh iteration not converged) are OR-ed into a device status word that
+ *    esvdw_get_status() reads back.
+ *  - Units are general: p = rho R T/(1 - b rho) - a rho^2, e = c_v T - a rho (eq. vdWEOS).
+ *    The paper's dimensionless units are (R, c_v, a, b) = (1, 1/delta, 9/8, 1/3); the
+ *    "reduced" units (8/3, (8/3)/delta, 3, 1/3) make the critical point (1, 1, 1).
+ */
+#ifndef ESVDW_H
+#define ESVDW_H
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ESVDW_OK 0
+#define ESVDW_EINVAL (-1)
+#define ESVDW_EHIP (-2)
+#define ESVDW_ENOTIMPL (-3)
+
+#define ESVDW_F_INADMISSIBLE 1u   /* a node state violates eq. coefflimit / eq. Tlimit */
+#define ESVDW_F_MEANCONSTRAINT 2u /* D <= 0 (Theorem 3.1) or a non-positive S^2 entry */
+#define ESVDW_F_NAN 4u            /* a NaN reached an output */
+#define ESVDW_F_NOTCONVERGED 8u   /* tolerance-mode mesh iteration hit its sweep cap */
+
+#define ESVDW_BC_PERIODIC 0
+#define ESVDW_BC_OUTFLOW 1 /* state: zero gradient; mesh: mirror about the boundary face */
+
+#define ESVDW_MON_VDW 0  /* monitor of Section 4 (squared gradient terms + |Delta G|^2) */
+#define ESVDW_MON_SINE 1 /* monitor of Example 5.1 (|grad rho|, |Delta rho|) */
+#define ESVDW_VAR_RHO 0
+#define ESVDW_VAR_G 1
+
+typedef struct esvdw_params {
+  int dim;              /* 1, 2 or 3 */
+  int n[3];             /* interior nodes per direction (>= 6 in active directions) */
+  double lo[3], hi[3];  /* computational box (equal to the physical box at t = 0) */
+  int bc[3];            /* ESVDW_BC_* per direction */
+  double R, cv, a, b;   /* gas constant, heat capacity, van der Waals a >= 0, b >= 0 */
+  int dissipation;      /* 0: entropy-conservative flux only; 1: entropy-stable flux */
+  double weno_lin[3];   /* MR-WENO linear weights of the 5-, 3-, 1-point levels (Section 5) */
+  double weno_eps;      /* MR-WENO epsilon (1e-10) */
+  double cfl;           /* eq. cfl; 0.4 in 1D/2D and 0.3 in 3D in the paper */
+  double dt_fixed;      /* > 0: use this time step instead of eq. cfl */
+  int monitor_kind;     /* ESVDW_MON_* */
+  int kappa;            /* number of gradient terms in the vdW monitor (0..2) */
+  int mon_var[2];       /* ESVDW_VAR_* of each gradient term */
+  double alpha[3];      /* alpha_1..alpha_{kappa+1} (sine monitor: alpha_1, alpha_2) */
+  int n_filter;         /* low-pass filter passes (3..10, 20 in the smooth tests) */
+  int mu;               /* Jacobi sweeps (fixed mode) or the sweep cap (tolerance mode) */
+  double mesh_tol;      /* tolerance of the Jacobi stop test (max node update) */
+  int fixed_mu;         /* 1: exactly mu sweeps; 0: stop once the update is < mesh_tol */
+} esvdw_params;
+
+typedef struct esvdw_ctx esvdw_ctx;
+
+/* Validates the parameters and allocates the context's scratch on the current device.
+ * Ownership of *out passes to the caller (release with esvdw_destroy).  EINVAL on bad
+ * parameters, EHIP on allocation failure. */
+int esvdw_create(const esvdw_params *p, esvdw_ctx **out);
+void esvdw_destroy(esvdw_ctx *ctx);
+
+/* Synchronises the device, copies the status word (ESVDW_F_* bits) to *flags_host and
+ * clears it when clear != 0. */
+int esvdw_get_status(esvdw_ctx *ctx, unsigned *flags_host, int clear);
+const char *esvdw_strerror(int code);
+
+/* Mesh at t = 0 (Section 3.2).  If uniform != 0, x (dim fields) is first set to the uniform
+ * mesh x = xi.  J (1 field) receives the discrete Jacobian det(dx/dxi) evaluated with the
+ * same sixth-order central operators delta_k as the metrics (eq. SCLCoeff): in 2D
+ * (delta_1[x_1] delta_2[x_2] - delta_2[x_1] delta_1[x_2])/(dxi_1 dxi_2). */
+int init_mesh(esvdw_ctx *ctx, double *x, double *J, int uniform, hipStream_t stream);
+
+/* JU = J U(prim) with prim = (rho, v_1..v_dim, p) fields and U = (rho, rho v, E),
+ * E = rho e + rho |v|^2/2 (eq. ConserLaw2, eq. vdWEOS). */
+int init_state(esvdw_ctx *ctx, const double *prim, const double *J, double *JU, hipStream_t stream);
+
+/* Discrete metrics of Section 3.2 at the interior nodes: met[(k*dim + j)] = J dxi_k/dx_j
+ * (eq. SCLCoeff; conservative nested form in 3D) and xit[k] = J dxi_k/dt =
+ * -sum_j xdot_j J dxi_k/dx_j (eq. VCLCoeff).  xdot may be NULL (static mesh: xit = 0). */
+int compute_metrics(esvdw_ctx *ctx, const double *x, const double *xdot, double *met, double *xit,
+                    hipStream_t stream);
+
+/* Semi-discrete right-hand side, eq. semi_U and eq. semi_J: dJU (nv fields) and dJ (1 field)
+ * from the state (JU, J) and interior metrics (met, xit as written by compute_metrics; xit
+ * may be NULL).  The interface flux is the sixth-order EC flux (eq. ECFlux_curv_2p built on
+ * the two-point flux eq. ECfluxMM) minus, if dissipation is on, the scaled-eigenvector
+ * MR-WENO dissipation of eq. HOstable.  Ghost metrics follow the boundary symmetry. */
+int es_rhs(esvdw_ctx *ctx, const double *JU, const double *J, const double *met, const double *xit,
+           double *dJU, double *dJ, hipStream_t stream);
+
+/* One third-order SSP Runge-Kutta stage s in {0, 1, 2} (Shu-Osher form) on the moving mesh:
+ * the RHS of the stage input (JUs, Js) is evaluated on the stage mesh x_n + c_s dt xdot,
+ * c = (0, 1, 1/2), with metrics computed in place from that mesh, then
+ *   s=0: out = in + dt L;  s=1: out = 3/4 base + 1/4 (in + dt L);  s=2: out = 1/3 base + 2/3 (in + dt L)
+ * with base = (JU0, J0).  dt_dev: device pointer to dt.  xdot may be NULL (static mesh).
+ * (JUout, Jout) may alias the base but not the stage input.  If s == 2 and x_next is not
+ * NULL, x_next = x_n + dt xdot (x_next may alias x_n). */
+int rk_stage(esvdw_ctx *ctx, int s, const double *dt_dev, const double *JU0, const double *J0,
+             const double *JUs, const double *Js, const double *x_n, const double *xdot, double *JUout,
+             double *Jout, double *x_next, hipStream_t stream);
+
+/* Mesh redistribution between time steps (Section 4): monitor omega from U^n (eq.
+ * van der Waalsmonitor or eq. van der Waalssinmonitor), n_filter low-pass passes, Jacobi
+ * iteration of the discretised eq. mesh_EL from x^[0] = x_n (+ warm_dx if not NULL) for mu
+ * sweeps (or to mesh_tol), the movement limiter Delta_gamma, the time step of eq. cfl (or
+ * dt_fixed), and finally xdot = Delta_gamma (x^[mu] - x_n)/dt.  Outputs: xdot (dim fields),
+ * *dt_dev, *resid_dev (max node update of the last sweep), *sweeps_dev (sweeps done); any of
+ * resid_dev / sweeps_dev may be NULL.  In tolerance mode the call synchronises the stream
+ * between sweep batches (not capturable). */
+int redistribute_mesh(esvdw_ctx *ctx, const double *JU, const double *J, const double *x_n,
+                      const double *warm_dx, double *xdot, double *dt_dev, double *resid_dev,
+                      int *sweeps_dev, hipStream_t stream);
+
+/* Building blocks of redistribute_mesh, exposed for tests and the learned warm start.
+ * mesh_monitor: omega (1 field) = filtered monitor from (JU, J).
+ * mesh_jacobi: nsweep Jacobi sweeps on x (dim fields, updated in place) with fixed omega;
+ *   *resid_dev = max node update of the last sweep (may be NULL).
+ * mesh_limiter: *gamma_dev = Delta_gamma for the move x_n -> x_mu.
+ * cfl_dt: *dt_dev = CFL / max_i sum_k L_k (|v . n_k| + c)/(J dxi_k) on the mesh x. */
+int mesh_monitor(esvdw_ctx *ctx, const double *JU, const double *J, double *omega, hipStream_t stream);
+int mesh_jacobi(esvdw_ctx *ctx, const double *omega, double *x, int nsweep, double *resid_dev,
+                hipStream_t stream);
+int mesh_limiter(esvdw_ctx *ctx, const double *x_n, const double *x_mu, double *gamma_dev, hipStream_t stream);
+int cfl_dt(esvdw_ctx *ctx, const double *JU, const double *J, const double *x, double *dt_dev,
+           hipStream_t stream);
+
+/* One complete time step in place: redistribute_mesh (fixed mu) when moving != 0, else the
+ * CFL time step on the fixed mesh; three rk_stage calls using the context's stage buffers;
+ * x <- x + dt xdot.  *dt_dev receives dt.  Capturable into a HIP graph. */
+int esvdw_step(esvdw_ctx *ctx, double *JU, double *J, double *x, int moving, double *dt_dev,
+               hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -759,8 +759,9 @@ static void interface_flux(const orc_cfg *c, double st[6][NVMAX], double mx[6][3
     double v = fabs(mtb + L * lam[q]);
     if (v > Lam) Lam = v;
   }
-  /* scaled entropy variables W_s = R^T T V_s on the stencil */
-  double W[6][NVMAX];
+  /* scaled entropy variables W_s = R^T T V_s on the stencil; Wmag_s = |R|^T |T V_s| bounds
+     the magnitude of the terms summed into W_s (used for the zero test of Y below) */
+  double W[6][NVMAX], Wmag[6][NVMAX];
   for (int s = 0; s < 6; ++s) {
     double V[NVMAX], TV[NVMAX];
     orc_entropy_vars(c, st[s], V);
@@ -770,18 +771,25 @@ static void interface_flux(const orc_cfg *c, double st[6][NVMAX], double mx[6][3
       TV[r] = a;
     }
     for (int r = 0; r < nv; ++r) {
-      double a = 0.0;
-      for (int q = 0; q < nv; ++q) a += Rm[q * NVMAX + r] * TV[q];
+      double a = 0.0, m = 0.0;
+      for (int q = 0; q < nv; ++q) {
+        a += Rm[q * NVMAX + r] * TV[q];
+        m += fabs(Rm[q * NVMAX + r]) * fabs(TV[q]);
+      }
       W[s][r] = a;
+      Wmag[s][r] = m;
     }
   }
-  /* jumps: plain [W] and reconstructed [W]^WENO = W+ - W-; sign matrix Y */
+  /* jumps: plain [W] and reconstructed [W]^WENO = W+ - W-; sign matrix Y.  A plain jump
+     below the rounding level of the terms that form W (2^-40 of their magnitude) is taken
+     as zero, so Y = 0 there: Y only gates dissipation, so the flux stays entropy stable. */
   double YdW[NVMAX];
   for (int r = 0; r < nv; ++r) {
     double Wm = orc_mrweno5(c, W[0][r], W[1][r], W[2][r], W[3][r], W[4][r]);
     double Wp = orc_mrweno5(c, W[5][r], W[4][r], W[3][r], W[2][r], W[1][r]);
     double jw = Wp - Wm;
     double j0 = W[3][r] - W[2][r];
+    if (fabs(j0) <= ldexp(Wmag[2][r] + Wmag[3][r], -40)) j0 = 0.0;
     int same = (jw > 0.0 && j0 > 0.0) || (jw < 0.0 && j0 < 0.0);
     YdW[r] = same ? jw : 0.0;
     *prod += 0.5 * Lam * j0 * YdW[r];

@@ -1,0 +1,218 @@
+// common.h -- device-side building blocks of the gfx950 library: grid geometry and
+// boundary index maps, the van der Waals thermodynamics, the logarithmic mean, the
+// multi-resolution WENO reconstruction and wavefront reductions.  FP64 throughout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/esvdw.h"
+
+#define MAXD 3
+#define MAXNV 5
+#define GH 3 /* ghost layers of node data (the stencils reach i-3 .. i+3) */
+
+struct Geo {
+  int dim, nv;
+  int n[3];    // interior nodes (1 in unused directions)
+  int g[3];    // ghost layers of the node buffer (GH in active directions)
+  int P[3];    // padded extents of the node buffer
+  long N, PN;  // interior / padded node counts
+  double lo[3], hi[3], dxi[3], idxi[3], period[3];
+  int bc[3];
+  double R, cv, a, b, delta;
+  double wl0, wl1, wl2, weps;
+  int diss;
+};
+
+// sixth-order central / high-order flux coefficients alpha_{3,m}: sum m a = 1, sum m^3 a = sum m^5 a = 0
+#define AL1 1.5
+#define AL2 (-0.3)
+#define AL3 (1.0 / 30.0)
+
+__device__ __forceinline__ int floordiv(int i, int n) { return i >= 0 ? i / n : -((-i + n - 1) / n); }
+
+// interior source of a (possibly ghost) state index along one direction
+__device__ __forceinline__ int state_src(int i, int n, int bc) {
+  if (i >= 0 && i < n) return i;
+  if (bc == ESVDW_BC_PERIODIC) return i - floordiv(i, n) * n;
+  return i < 0 ? 0 : n - 1;
+}
+
+__device__ __forceinline__ long lin(const Geo &G, int i0, int i1, int i2) {
+  return ((long)i2 * G.n[1] + i1) * G.n[0] + i0;
+}
+
+__device__ __forceinline__ long state_index(const Geo &G, int i0, int i1, int i2) {
+  return lin(G, state_src(i0, G.n[0], G.bc[0]), state_src(i1, G.n[1], G.bc[1]), state_src(i2, G.n[2], G.bc[2]));
+}
+
+// Mesh coordinate j at any index within the ghost reach: periodic directions wrap with a
+// shift of one period per wrap (only for the coordinate along that direction); outflow
+// directions mirror about the boundary face (the coordinate along the direction is odd,
+// the others even).  vel != 0: a mesh velocity component (no shift, same parity).
+__device__ __forceinline__ double mesh_at(const Geo &G, const double *__restrict__ x, int j, int i0, int i1,
+                                          int i2, int vel) {
+  int ii[3] = {i0, i1, i2};
+  double sg = 1.0, off = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (k >= G.dim) break;
+    int i = ii[k], n = G.n[k];
+    if (i >= 0 && i < n) continue;
+    if (G.bc[k] == ESVDW_BC_PERIODIC) {
+      int q = floordiv(i, n);
+      ii[k] = i - q * n;
+      if (k == j && !vel) off = q * G.period[k];
+    } else {
+      ii[k] = i < 0 ? -1 - i : 2 * n - 1 - i;
+      if (k == j) {
+        sg = -1.0;
+        if (!vel) off = 2.0 * (i < 0 ? G.lo[k] : G.hi[k]);
+      }
+    }
+  }
+  return sg * x[(long)j * G.N + lin(G, ii[0], ii[1], ii[2])] + off;
+}
+
+// ---------------------------------------------------------------------------------
+// thermodynamics (eq. vdWEOS and the closed forms of Section 2, general units)
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ double eos_p(const Geo &G, double rho, double T) {
+  return rho * G.R * T / (1.0 - G.b * rho) - G.a * rho * rho;
+}
+__device__ __forceinline__ double eos_T_rho_e(const Geo &G, double rho, double e) { return (e + G.a * rho) / G.cv; }
+__device__ __forceinline__ double eos_T_rho_p(const Geo &G, double rho, double p) {
+  return (p + G.a * rho * rho) * (1.0 - G.b * rho) / (G.R * rho);
+}
+__device__ __forceinline__ double eos_c2(const Geo &G, double rho, double T) {
+  double ob = 1.0 - G.b * rho;
+  return (1.0 + G.delta) * G.R * T / (ob * ob) - 2.0 * G.a * rho;
+}
+__device__ __forceinline__ double eos_G(const Geo &G, double rho, double T) {
+  double ob = 1.0 - G.b * rho;
+  return ((1.0 + G.delta) * (2.0 + G.delta) * G.R * T / (ob * ob * ob) - 6.0 * G.a * rho) / (2.0 * eos_c2(G, rho, T));
+}
+// eq. coefflimit / eq. Tlimit
+__device__ __forceinline__ bool admissible(const Geo &G, double rho, double T) {
+  double ob = 1.0 - G.b * rho;
+  bool ok = rho > 0.0 && ob > 0.0;
+  ok = ok && (G.b > 0.0 ? T * 4.0 * G.R * G.b > G.a : T > 0.0);
+  return ok && (G.R * T - 2.0 * G.a * rho * ob * ob > 0.0);
+}
+
+// logarithmic mean (a_r - a_l)/(ln a_r - ln a_l) = (a_l + a_r)/(2 atanh(f)/f), f = (a_r - a_l)/(a_r + a_l);
+// atanh(f)/f by its Taylor series when f^2 < 1e-4, else by log1p.
+__device__ __forceinline__ double logmean(double al, double ar) {
+  double s = al + ar;
+  double f = (ar - al) / s;
+  double u = f * f;
+  double h;
+  if (u < 1e-4) {
+    h = 1.0 + u * (1.0 / 3.0 + u * (1.0 / 5.0 + u * (1.0 / 7.0 + u * (1.0 / 9.0))));
+  } else {
+    h = 0.5 * log1p(2.0 * f / (1.0 - f)) / f;
+  }
+  return 0.5 * s / h;
+}
+
+// Multi-resolution WENO, fifth order: left limit at the right face of the centre cell of
+// (a, b, c, d, e) = w_{i-2..i+2}.  Hierarchy of central levels: 1 point (w_i), 3 points
+// (quadratic), 5 points (quartic) with linear weights wl2, wl1, wl0.
+__device__ __forceinline__ double mrweno5(const Geo &G, double a, double b, double c, double d, double e) {
+  double q5 = (2.0 * a - 13.0 * b + 47.0 * c + 27.0 * d - 3.0 * e) * (1.0 / 60.0);
+  double q3 = (-b + 5.0 * c + 2.0 * d) * (1.0 / 6.0);
+  double dl = c - b, dr = d - c;
+  double s1 = fmin(dl * dl, dr * dr);
+  double t1 = b - 2.0 * c + d, t2 = d - b;
+  double s3 = (13.0 / 12.0) * t1 * t1 + 0.25 * t2 * t2;
+  // Jiang-Shu functional of the quartic, as a quadratic form in (a..e)
+  double s5 = (c * (231153.0 * c - 299076.0 * (b + d) + 67923.0 * (a + e)) + 104963.0 * (b * b + d * d) -
+               51001.0 * (a * b + d * e) + 179098.0 * b * d - 38947.0 * (b * e + a * d) + 6908.0 * (a * a + e * e) +
+               8209.0 * a * e) *
+              (1.0 / 5040.0);
+  double tt = 0.5 * (fabs(s5 - s1) + fabs(s5 - s3));
+  double tau = tt * tt;
+  double w5 = G.wl0 * (1.0 + tau / (s5 + G.weps));
+  double w3 = G.wl1 * (1.0 + tau / (s3 + G.weps));
+  double w1 = G.wl2 * (1.0 + tau / (s1 + G.weps));
+  double inv = 1.0 / (w5 + w3 + w1);
+  double top = (q5 - G.wl1 * q3 - G.wl2 * c) / G.wl0;
+  return (w5 * top + w3 * q3 + w1 * c) * inv;
+}
+
+// ---------------------------------------------------------------------------------
+// reductions: wavefront (64 lanes) by shuffles, then across the block through LDS,
+// then one device atomic per block on the bit pattern of a non-negative double
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// block of at most 1024 threads; v >= 0
+__device__ __forceinline__ void block_atomic_max(double v, double *dst) {
+  __shared__ double part[16];
+  v = wave_max(v);
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) part[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int nw = (blockDim.x + 63) >> 6;
+    double m = part[0];
+    for (int i = 1; i < nw; ++i) m = fmax(m, part[i]);
+    if (m > 0.0) atomicMax((unsigned long long *)dst, (unsigned long long)__double_as_longlong(m));
+  }
+}
+__device__ __forceinline__ void block_atomic_min(double v, double *dst) {
+  __shared__ double part[16];
+  v = wave_min(v);
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) part[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int nw = (blockDim.x + 63) >> 6;
+    double m = part[0];
+    for (int i = 1; i < nw; ++i) m = fmin(m, part[i]);
+    atomicMin((unsigned long long *)dst, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+__device__ __forceinline__ void raise_flag(unsigned *flags, unsigned f) { atomicOr(flags, f); }
+
+// device scalar slots of a context
+enum { SC_CFL = 0, SC_MON = 1, SC_GAMMA = 4, SC_RESID = 5, SC_DT = 6, SC_N = 8 };
+
+// ---------------------------------------------------------------------------------
+// host-side context
+// ---------------------------------------------------------------------------------
+struct esvdw_ctx {
+  esvdw_params p;
+  Geo G;
+  int dev;
+  int NF;            // node-buffer fields
+  double *node;      // NF * PN padded node data
+  double *flux[3];   // per direction: (nv + 1) * interfaces
+  long nif[3];       // interfaces per direction
+  double *dprod;     // 3D: 9 fields of delta_q[x_r] on a 6-ghost padded grid
+  long dpN;          // padded node count of dprod
+  double *met;       // dim*dim + dim fields (interior), scratch for cfl/jacobian
+  double *stA, *stB; // RK stage buffers, (nv + 1) * N each
+  double *xdot, *xmu, *xtmp;  // dim * N each
+  double *omega, *omega2, *mterm;  // N, N, 3N
+  double *rhoG;      // 2N
+  double *scal;      // SC_N doubles
+  unsigned *flags;
+};
+
+// node-buffer field offsets for dimension D
+template <int D> struct NF_ {
+  static constexpr int RHO = 0, V = 1, T = D + 1, P = D + 2, IT = D + 3, GG = D + 4, VS = D + 5, MS = VS + D + 2,
+                       XS = MS + D * D, COUNT = XS + D;
+};

@@ -1,0 +1,25 @@
+// kernels.h -- launchers shared between the translation units of the library
+#pragma once
+#include "common.h"
+
+int launch_dprod(esvdw_ctx *c, const double *xn, const double *xd, double cdt, hipStream_t st);
+int launch_metrics(esvdw_ctx *c, const double *x, const double *xd, double *met, double *xit, double *J,
+                   hipStream_t st);
+int launch_rhs(esvdw_ctx *c, const double *JU, const double *J, const double *met, const double *xit,
+               const double *xn, const double *xd, double cdt, int mode, int s, const double *dtp,
+               const double *bJU, const double *bJ, double *oJU, double *oJ, hipStream_t st);
+int launch_uniform_mesh(esvdw_ctx *c, double *x, hipStream_t st);
+int launch_init_state(esvdw_ctx *c, const double *prim, const double *J, double *JU, hipStream_t st);
+int launch_axpy_mesh(esvdw_ctx *c, const double *x, const double *xd, const double *dtp, double f, double *out,
+                     hipStream_t st);
+int launch_set_int(int *p, int v, hipStream_t st);
+
+int launch_set_scalars(esvdw_ctx *c, hipStream_t st);
+int launch_monitor(esvdw_ctx *c, const double *JU, const double *J, double *omega, hipStream_t st);
+int launch_jacobi(esvdw_ctx *c, const double *omega, double *x, int nsweep, double *resid_dev, hipStream_t st);
+int launch_limiter(esvdw_ctx *c, const double *xn, const double *xmu, double *gamma_dev, hipStream_t st);
+int launch_cfl(esvdw_ctx *c, const double *JU, const double *J, const double *x, double *dt_dev, hipStream_t st);
+int launch_xdot(esvdw_ctx *c, const double *xn, const double *xmu, const double *gam, const double *dtp, double *xdot,
+                hipStream_t st);
+int launch_copy(const double *src, double *dst, long n, hipStream_t st);
+int launch_add(const double *a, const double *b, double *dst, long n, hipStream_t st);

@@ -1,0 +1,346 @@
+// mesh.hip -- adaptive moving mesh (Section 4): monitor, low-pass filter, Jacobi sweeps
+// of the discretised Winslow equations, movement limiter, CFL time step (eq. cfl) and the
+// mesh velocity.  All global reductions are wavefront shuffles + one atomic per block on a
+// device scalar of the context.
+#include "common.h"
+#include "kernels.h"
+
+static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+__device__ __forceinline__ void coords(const Geo &G, long t, int &i0, int &i1, int &i2) {
+  i0 = (int)(t % G.n[0]);
+  i1 = (int)((t / G.n[0]) % G.n[1]);
+  i2 = (int)(t / ((long)G.n[0] * G.n[1]));
+}
+
+__global__ void k_set_scalars(double *s) {
+  if (threadIdx.x == 0) {
+    s[SC_CFL] = 0.0;
+    s[SC_MON] = s[SC_MON + 1] = s[SC_MON + 2] = 0.0;
+    s[SC_GAMMA] = 1.0;
+    s[SC_RESID] = 0.0;
+  }
+}
+
+__global__ void k_set1(double *p, double v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+__global__ void k_set_int(int *p, int v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+__global__ void k_copy(const double *__restrict__ a, double *__restrict__ b, long n) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t < n) b[t] = a[t];
+}
+
+__global__ void k_add(const double *__restrict__ a, const double *__restrict__ b, double *__restrict__ c, long n) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t < n) c[t] = a[t] + b[t];
+}
+
+// ---- monitor -------------------------------------------------------------------
+template <int D>
+__global__ void k_rho_G(Geo G, const double *__restrict__ JU, const double *__restrict__ J, double *__restrict__ rg) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= G.N) return;
+  double iJ = 1.0 / J[t];
+  double rho = JU[t] * iJ, v2 = 0.0;
+  for (int m = 0; m < D; ++m) {
+    double v = JU[(long)(1 + m) * G.N + t] * iJ / rho;
+    v2 += v * v;
+  }
+  double T = eos_T_rho_e(G, rho, JU[(long)(D + 1) * G.N + t] * iJ / rho - 0.5 * v2);
+  rg[t] = rho;
+  rg[G.N + t] = eos_G(G, rho, T);
+}
+
+// term t of the monitor at each node; maxima into scal[SC_MON + t]
+template <int D>
+__global__ void k_mon_terms(Geo G, int kind, int kappa, int var0, int var1, const double *__restrict__ rg,
+                            double *__restrict__ term, double *scal) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  int nterm = kind == ESVDW_MON_VDW ? kappa + 1 : 2;
+  double val[3] = {0.0, 0.0, 0.0};
+  if (t < G.N) {
+    int i0, i1, i2;
+    coords(G, t, i0, i1, i2);
+    for (int q = 0; q < nterm; ++q) {
+      const double *f;
+      bool second;
+      if (kind == ESVDW_MON_VDW) {
+        if (q < kappa) {
+          f = ((q == 0 ? var0 : var1) == ESVDW_VAR_G) ? rg + G.N : rg;
+          second = false;
+        } else {
+          f = rg + G.N;
+          second = true;
+        }
+      } else {
+        f = rg;
+        second = q == 1;
+      }
+      double f0 = f[t], s2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        int e0 = k == 0, e1 = k == 1, e2 = k == 2;
+        double fp = f[state_index(G, i0 + e0, i1 + e1, i2 + e2)];
+        double fm = f[state_index(G, i0 - e0, i1 - e1, i2 - e2)];
+        double g = second ? (fp - 2.0 * f0 + fm) * G.idxi[k] * G.idxi[k] : (fp - fm) * 0.5 * G.idxi[k];
+        s2 += g * g;
+      }
+      val[q] = kind == ESVDW_MON_VDW ? s2 : sqrt(s2);
+      term[(long)q * G.N + t] = val[q];
+    }
+  }
+  for (int q = 0; q < 3; ++q) {
+    if (q >= nterm) break;
+    block_atomic_max(val[q], scal + SC_MON + q);
+    __syncthreads();
+  }
+}
+
+__global__ void k_mon_omega(Geo G, int nterm, double a0, double a1, double a2, const double *__restrict__ term,
+                            const double *__restrict__ scal, double *__restrict__ omega) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= G.N) return;
+  double al[3] = {a0, a1, a2};
+  double s = 1.0;
+  for (int q = 0; q < nterm; ++q) {
+    double m = scal[SC_MON + q];
+    if (m > 0.0) s += al[q] * term[(long)q * G.N + t] / m;
+  }
+  omega[t] = sqrt(s);
+}
+
+// omega <- sum_{j in {-1,0,1}^d} 2^-(|j|_1 + d) omega_{i+j}; replicate / wrap at the boundary
+template <int D>
+__global__ void k_filter(Geo G, const double *__restrict__ in, double *__restrict__ out) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= G.N) return;
+  int i0, i1, i2;
+  coords(G, t, i0, i1, i2);
+  double s = 0.0;
+  const int r1 = D > 1, r2 = D > 2;
+  for (int j2 = -r2; j2 <= r2; ++j2)
+    for (int j1 = -r1; j1 <= r1; ++j1)
+#pragma unroll
+      for (int j0 = -1; j0 <= 1; ++j0) {
+        int l1 = (j0 != 0) + (j1 != 0) + (j2 != 0) + D;
+        s += ldexp(1.0, -l1) * in[state_index(G, i0 + j0, i1 + j1, i2 + j2)];
+      }
+  out[t] = s;
+}
+
+// ---- Jacobi sweep -----------------------------------------------------------------
+template <int D>
+__global__ void k_jacobi(Geo G, const double *__restrict__ omega, const double *__restrict__ xin,
+                         double *__restrict__ xout, double *resid) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  double r = 0.0;
+  if (t < G.N) {
+    int i0, i1, i2;
+    coords(G, t, i0, i1, i2);
+    double w0 = omega[t];
+    double den = 0.0, num[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) num[j] = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      int e0 = k == 0, e1 = k == 1, e2 = k == 2;
+      double h2 = G.idxi[k] * G.idxi[k];
+      double wp = 0.5 * (w0 + omega[state_index(G, i0 + e0, i1 + e1, i2 + e2)]) * h2;
+      double wm = 0.5 * (w0 + omega[state_index(G, i0 - e0, i1 - e1, i2 - e2)]) * h2;
+      den += wp + wm;
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+        num[j] += wp * mesh_at(G, xin, j, i0 + e0, i1 + e1, i2 + e2, 0) +
+                  wm * mesh_at(G, xin, j, i0 - e0, i1 - e1, i2 - e2, 0);
+    }
+    double iden = 1.0 / den;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      double v = num[j] * iden;
+      r = fmax(r, fabs(v - xin[(long)j * G.N + t]));
+      xout[(long)j * G.N + t] = v;
+    }
+  }
+  if (resid) block_atomic_max(r, resid);
+}
+
+// ---- limiter ----------------------------------------------------------------------
+template <int D>
+__global__ void k_limiter(Geo G, const double *__restrict__ xn, const double *__restrict__ xmu, double *gam) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  double g = 1.0;
+  if (t < G.N) {
+    int i0, i1, i2;
+    coords(G, t, i0, i1, i2);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      int e0 = k == 0, e1 = k == 1, e2 = k == 2;
+      double x0 = xn[(long)k * G.N + t];
+      double dx = xmu[(long)k * G.N + t] - x0;
+      if (dx < 0.0) g = fmin(g, -(x0 - mesh_at(G, xn, k, i0 - e0, i1 - e1, i2 - e2, 0)) / (2.0 * dx));
+      else if (dx > 0.0) g = fmin(g, (mesh_at(G, xn, k, i0 + e0, i1 + e1, i2 + e2, 0) - x0) / (2.0 * dx));
+    }
+  }
+  block_atomic_min(g, gam);
+}
+
+// ---- CFL ----------------------------------------------------------------------------
+template <int D>
+__global__ void k_cfl(Geo G, const double *__restrict__ JU, const double *__restrict__ J,
+                      const double *__restrict__ met, double *mx) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (t < G.N) {
+    double iJ = 1.0 / J[t];
+    double rho = JU[t] * iJ, v[D], v2 = 0.0;
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+      v[m] = JU[(long)(1 + m) * G.N + t] * iJ / rho;
+      v2 += v[m] * v[m];
+    }
+    double T = eos_T_rho_e(G, rho, JU[(long)(D + 1) * G.N + t] * iJ / rho - 0.5 * v2);
+    double c = sqrt(eos_c2(G, rho, T));
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      double L2 = 0.0, vn = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        double m = met[(long)(k * D + j) * G.N + t];
+        L2 += m * m;
+        vn += m * v[j];
+      }
+      s += (fabs(vn) + sqrt(L2) * c) * iJ * G.idxi[k];
+    }
+  }
+  block_atomic_max(s, mx);
+}
+
+__global__ void k_dt(double cfl, double dt_fixed, double *scal, double *dt_out) {
+  if (threadIdx.x == 0) {
+    double dt = dt_fixed > 0.0 ? dt_fixed : cfl / scal[SC_CFL];
+    scal[SC_DT] = dt;
+    if (dt_out) *dt_out = dt;
+  }
+}
+
+__global__ void k_xdot(long n, const double *__restrict__ xn, const double *__restrict__ xmu,
+                       const double *__restrict__ gam, const double *__restrict__ dtp, double *__restrict__ xd) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t < n) xd[t] = (*gam) * (xmu[t] - xn[t]) / (*dtp);
+}
+
+// ---- launchers ----------------------------------------------------------------------
+#define CHK() (hipGetLastError() == hipSuccess ? 0 : -1)
+
+int launch_set_scalars(esvdw_ctx *c, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, st, c->scal);
+  return CHK();
+}
+
+int launch_set_int(int *p, int v, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, p, v);
+  return CHK();
+}
+
+int launch_copy(const double *src, double *dst, long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy, dim3(nblk(n, 256)), dim3(256), 0, st, src, dst, n);
+  return CHK();
+}
+
+int launch_add(const double *a, const double *b, double *dst, long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_add, dim3(nblk(n, 256)), dim3(256), 0, st, a, b, dst, n);
+  return CHK();
+}
+
+template <int D> static int monitor_d(esvdw_ctx *c, const double *JU, const double *J, double *omega, hipStream_t st) {
+  const Geo &G = c->G;
+  const esvdw_params &p = c->p;
+  dim3 b(256), g(nblk(G.N, 256));
+  hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, st, c->scal);
+  hipLaunchKernelGGL(k_rho_G<D>, g, b, 0, st, G, JU, J, c->rhoG);
+  int nterm = p.monitor_kind == ESVDW_MON_VDW ? p.kappa + 1 : 2;
+  hipLaunchKernelGGL(k_mon_terms<D>, g, b, 0, st, G, p.monitor_kind, p.kappa, p.mon_var[0], p.mon_var[1], c->rhoG,
+                     c->mterm, c->scal);
+  // filtered result must end in `omega`: start in omega2 when the pass count is odd
+  double *cur = (p.n_filter % 2) ? c->omega2 : omega;
+  double *oth = (p.n_filter % 2) ? omega : c->omega2;
+  hipLaunchKernelGGL(k_mon_omega, g, b, 0, st, G, nterm, p.alpha[0], p.alpha[1], p.alpha[2], c->mterm, c->scal, cur);
+  for (int i = 0; i < p.n_filter; ++i) {
+    hipLaunchKernelGGL(k_filter<D>, g, b, 0, st, G, cur, oth);
+    double *tmp = cur;
+    cur = oth;
+    oth = tmp;
+  }
+  return CHK();
+}
+
+int launch_monitor(esvdw_ctx *c, const double *JU, const double *J, double *omega, hipStream_t st) {
+  switch (c->G.dim) {
+    case 1: return monitor_d<1>(c, JU, J, omega, st);
+    case 2: return monitor_d<2>(c, JU, J, omega, st);
+    default: return monitor_d<3>(c, JU, J, omega, st);
+  }
+}
+
+template <int D>
+static int jacobi_d(esvdw_ctx *c, const double *omega, double *x, int nsweep, double *resid_dev, hipStream_t st) {
+  const Geo &G = c->G;
+  dim3 b(256), g(nblk(G.N, 256));
+  double *a = x, *o = c->xtmp;
+  for (int it = 0; it < nsweep; ++it) {
+    bool last = it == nsweep - 1;
+    if (last) hipLaunchKernelGGL(k_set1, dim3(1), dim3(64), 0, st, c->scal + SC_RESID, 0.0);
+    hipLaunchKernelGGL(k_jacobi<D>, g, b, 0, st, G, omega, a, o, last ? c->scal + SC_RESID : nullptr);
+    double *tmp = a;
+    a = o;
+    o = tmp;
+  }
+  if (a != x) launch_copy(a, x, (long)D * G.N, st);
+  if (resid_dev) launch_copy(c->scal + SC_RESID, resid_dev, 1, st);
+  return CHK();
+}
+
+int launch_jacobi(esvdw_ctx *c, const double *omega, double *x, int nsweep, double *resid_dev, hipStream_t st) {
+  switch (c->G.dim) {
+    case 1: return jacobi_d<1>(c, omega, x, nsweep, resid_dev, st);
+    case 2: return jacobi_d<2>(c, omega, x, nsweep, resid_dev, st);
+    default: return jacobi_d<3>(c, omega, x, nsweep, resid_dev, st);
+  }
+}
+
+int launch_limiter(esvdw_ctx *c, const double *xn, const double *xmu, double *gamma_dev, hipStream_t st) {
+  const Geo &G = c->G;
+  dim3 b(256), g(nblk(G.N, 256));
+  hipLaunchKernelGGL(k_set1, dim3(1), dim3(64), 0, st, c->scal + SC_GAMMA, 1.0);
+  if (G.dim == 1) hipLaunchKernelGGL(k_limiter<1>, g, b, 0, st, G, xn, xmu, c->scal + SC_GAMMA);
+  else if (G.dim == 2) hipLaunchKernelGGL(k_limiter<2>, g, b, 0, st, G, xn, xmu, c->scal + SC_GAMMA);
+  else hipLaunchKernelGGL(k_limiter<3>, g, b, 0, st, G, xn, xmu, c->scal + SC_GAMMA);
+  if (gamma_dev) launch_copy(c->scal + SC_GAMMA, gamma_dev, 1, st);
+  return CHK();
+}
+
+int launch_cfl(esvdw_ctx *c, const double *JU, const double *J, const double *x, double *dt_dev, hipStream_t st) {
+  const Geo &G = c->G;
+  dim3 b(256), g(nblk(G.N, 256));
+  if (c->p.dt_fixed <= 0.0) {
+    if (launch_metrics(c, x, nullptr, c->met, nullptr, nullptr, st)) return -1;
+    hipLaunchKernelGGL(k_set1, dim3(1), dim3(64), 0, st, c->scal + SC_CFL, 0.0);
+    if (G.dim == 1) hipLaunchKernelGGL(k_cfl<1>, g, b, 0, st, G, JU, J, c->met, c->scal + SC_CFL);
+    else if (G.dim == 2) hipLaunchKernelGGL(k_cfl<2>, g, b, 0, st, G, JU, J, c->met, c->scal + SC_CFL);
+    else hipLaunchKernelGGL(k_cfl<3>, g, b, 0, st, G, JU, J, c->met, c->scal + SC_CFL);
+  }
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(64), 0, st, c->p.cfl, c->p.dt_fixed, c->scal, dt_dev);
+  return CHK();
+}
+
+int launch_xdot(esvdw_ctx *c, const double *xn, const double *xmu, const double *gam, const double *dtp, double *xdot,
+                hipStream_t st) {
+  long n = (long)c->G.dim * c->G.N;
+  hipLaunchKernelGGL(k_xdot, dim3(nblk(n, 256)), dim3(256), 0, st, n, xn, xmu, gam, dtp, xdot);
+  return CHK();
+}

@@ -1,0 +1,653 @@
+// rhs.hip -- metrics, node thermodynamics, interface fluxes and the RK-stage update of the
+// entropy-stable moving-mesh scheme (Sections 3.1-3.3).  One launch pipeline per RHS:
+//   k_dprod (3D only)  delta_q[x_r] on the stage mesh
+//   k_nodes            per padded node: primitives, 1/T, g, entropy variables, metrics
+//   k_flux<K>          per interface along K: sixth-order EC flux + MR-WENO dissipation
+//   k_update           flux differences, optional SSP-RK3 combination
+#include "common.h"
+#include "kernels.h"
+
+// =============================== metrics ========================================
+
+// stage-mesh coordinate: x_n + cdt * xdot, both ghost-extended by the mesh maps
+__device__ __forceinline__ double stage_x(const Geo &G, const double *__restrict__ xn, const double *__restrict__ xd,
+                                          double cdt, int j, int i0, int i1, int i2) {
+  double v = mesh_at(G, xn, j, i0, i1, i2, 0);
+  if (xd) v += cdt * mesh_at(G, xd, j, i0, i1, i2, 1);
+  return v;
+}
+
+// delta_k[x_j] at (i0, i1, i2): (1/2) sum_m alpha_m (x_{i+m e_k} - x_{i-m e_k})
+__device__ __forceinline__ double delta_x(const Geo &G, const double *xn, const double *xd, double cdt, int k, int j,
+                                          int i0, int i1, int i2) {
+  int e0 = k == 0, e1 = k == 1, e2 = k == 2;
+  double s = 0.0;
+  const double al[3] = {AL1, AL2, AL3};
+#pragma unroll
+  for (int m = 1; m <= 3; ++m)
+    s += al[m - 1] * (stage_x(G, xn, xd, cdt, j, i0 + m * e0, i1 + m * e1, i2 + m * e2) -
+                      stage_x(G, xn, xd, cdt, j, i0 - m * e0, i1 - m * e1, i2 - m * e2));
+  return 0.5 * s;
+}
+
+// 3D: dprod[q*3 + r] = delta_q[x_r] on a grid padded by 6 in every direction (valid where
+// the q index is within 3 of the interior, which is where it is used)
+__global__ void k_dprod(Geo G, const double *__restrict__ xn, const double *__restrict__ xd, double cdt,
+                        double *__restrict__ dp, long dpN) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= dpN) return;
+  int P0 = G.n[0] + 12, P1 = G.n[1] + 12;
+  int i0 = (int)(t % P0) - 6, i1 = (int)((t / P0) % P1) - 6, i2 = (int)(t / ((long)P0 * P1)) - 6;
+  int ii[3] = {i0, i1, i2};
+  for (int q = 0; q < 3; ++q) {
+    bool ok = ii[q] >= -3 && ii[q] < G.n[q] + 3;
+    for (int r = 0; r < 3; ++r) dp[(long)(q * 3 + r) * dpN + t] = ok ? delta_x(G, xn, xd, cdt, q, r, i0, i1, i2) : 0.0;
+  }
+}
+
+__device__ __forceinline__ long dp_index(const Geo &G, int i0, int i1, int i2) {
+  int P0 = G.n[0] + 12, P1 = G.n[1] + 12;
+  return ((long)(i2 + 6) * P1 + (i1 + 6)) * P0 + (i0 + 6);
+}
+
+// metric J dxi_k/dx_j at (i0, i1, i2) from the stage mesh (2D directly, 3D from dprod)
+template <int D>
+__device__ __forceinline__ double metric_at(const Geo &G, const double *xn, const double *xd, double cdt,
+                                            const double *dp, long dpN, int k, int j, int i0, int i1, int i2) {
+  if (D == 1) return 1.0;
+  if (D == 2) {
+    // J dxi_1/dx_1 = x_2,xi2 ; J dxi_1/dx_2 = -x_1,xi2 ; J dxi_2/dx_1 = -x_2,xi1 ; J dxi_2/dx_2 = x_1,xi1
+    int kk = 1 - k, jj = 1 - j;
+    double sg = (k == j) ? 1.0 : -1.0;
+    return sg * delta_x(G, xn, xd, cdt, kk, jj, i0, i1, i2) * G.idxi[kk];
+  }
+  // D == 3: (delta_{k2}[delta_{k1}[x_{j1}] x_{j2}] - delta_{k1}[delta_{k2}[x_{j1}] x_{j2}]) / (dxi_{k1} dxi_{k2})
+  int k1 = (k + 1) % 3, k2 = (k + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+  const double al[3] = {AL1, AL2, AL3};
+  double s = 0.0;
+  for (int term = 0; term < 2; ++term) {
+    int in = term == 0 ? k1 : k2, out = term == 0 ? k2 : k1;
+    int e[3] = {out == 0, out == 1, out == 2};
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 1; m <= 3; ++m) {
+      int a0 = i0 + m * e[0], a1 = i1 + m * e[1], a2 = i2 + m * e[2];
+      int b0 = i0 - m * e[0], b1 = i1 - m * e[1], b2 = i2 - m * e[2];
+      double fa = dp[(long)(in * 3 + j1) * dpN + dp_index(G, a0, a1, a2)] * stage_x(G, xn, xd, cdt, j2, a0, a1, a2);
+      double fb = dp[(long)(in * 3 + j1) * dpN + dp_index(G, b0, b1, b2)] * stage_x(G, xn, xd, cdt, j2, b0, b1, b2);
+      acc += al[m - 1] * (fa - fb);
+    }
+    s += (term == 0 ? 0.5 : -0.5) * acc;
+  }
+  return s * G.idxi[k1] * G.idxi[k2];
+}
+
+// interior metrics (compute_metrics) and, optionally, the Jacobian (init_mesh)
+template <int D>
+__global__ void k_metrics(Geo G, const double *__restrict__ xn, const double *__restrict__ xd,
+                          const double *__restrict__ dp, long dpN, double *__restrict__ met,
+                          double *__restrict__ xit, double *__restrict__ J) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= G.N) return;
+  int i0 = (int)(t % G.n[0]), i1 = (int)((t / G.n[0]) % G.n[1]), i2 = (int)(t / ((long)G.n[0] * G.n[1]));
+  double m[D][D];
+  for (int k = 0; k < D; ++k)
+    for (int j = 0; j < D; ++j) m[k][j] = metric_at<D>(G, xn, nullptr, 0.0, dp, dpN, k, j, i0, i1, i2);
+  if (met)
+    for (int k = 0; k < D; ++k)
+      for (int j = 0; j < D; ++j) met[(long)(k * D + j) * G.N + t] = m[k][j];
+  if (xit) {
+    for (int k = 0; k < D; ++k) {
+      double s = 0.0;
+      if (xd)
+        for (int j = 0; j < D; ++j) s -= xd[(long)j * G.N + t] * m[k][j];
+      xit[(long)k * G.N + t] = s;
+    }
+  }
+  if (J) {
+    double v;
+    if (D == 1) {
+      v = delta_x(G, xn, nullptr, 0.0, 0, 0, i0, i1, i2) * G.idxi[0];
+    } else if (D == 2) {
+      v = (delta_x(G, xn, nullptr, 0.0, 0, 0, i0, i1, i2) * delta_x(G, xn, nullptr, 0.0, 1, 1, i0, i1, i2) -
+           delta_x(G, xn, nullptr, 0.0, 1, 0, i0, i1, i2) * delta_x(G, xn, nullptr, 0.0, 0, 1, i0, i1, i2)) *
+          G.idxi[0] * G.idxi[1];
+    } else {
+      v = 0.0;
+      for (int j = 0; j < D; ++j) v += delta_x(G, xn, nullptr, 0.0, 0, j, i0, i1, i2) * G.idxi[0] * m[0][j];
+    }
+    J[t] = v;
+  }
+}
+
+// =============================== node data =======================================
+
+// Metrics given at interior nodes only (es_rhs): ghost values by the boundary symmetry.
+// Outflow mirror normal to q flips J dxi_k/dx_j iff exactly one of k, j is q, and J dxi_k/dt iff k = q.
+__device__ __forceinline__ long ghost_metric_src(const Geo &G, int i0, int i1, int i2, unsigned &mirror) {
+  int ii[3] = {i0, i1, i2};
+  mirror = 0;
+  for (int q = 0; q < G.dim; ++q) {
+    int i = ii[q], n = G.n[q];
+    if (i >= 0 && i < n) continue;
+    if (G.bc[q] == ESVDW_BC_PERIODIC) {
+      ii[q] = i - floordiv(i, n) * n;
+    } else {
+      ii[q] = i < 0 ? -1 - i : 2 * n - 1 - i;
+      mirror |= 1u << q;
+    }
+  }
+  return lin(G, ii[0], ii[1], ii[2]);
+}
+
+template <int D>
+__global__ void k_nodes(Geo G, const double *__restrict__ JU, const double *__restrict__ J,
+                        const double *__restrict__ met_in, const double *__restrict__ xit_in,
+                        const double *__restrict__ xn, const double *__restrict__ xd, double cdt,
+                        const double *__restrict__ dp, long dpN, double *__restrict__ nd, unsigned *flags) {
+  using F = NF_<D>;
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= G.PN) return;
+  int p0 = (int)(t % G.P[0]), p1 = (int)((t / G.P[0]) % G.P[1]), p2 = (int)(t / ((long)G.P[0] * G.P[1]));
+  int i0 = p0 - G.g[0], i1 = p1 - G.g[1], i2 = p2 - G.g[2];
+  long s = state_index(G, i0, i1, i2);
+  double iJ = 1.0 / J[s];
+  double rho = JU[s] * iJ;
+  double v[D], v2 = 0.0;
+#pragma unroll
+  for (int m = 0; m < D; ++m) {
+    v[m] = JU[(long)(1 + m) * G.N + s] * iJ / rho;
+    v2 += v[m] * v[m];
+  }
+  double e = JU[(long)(D + 1) * G.N + s] * iJ / rho - 0.5 * v2;
+  double T = eos_T_rho_e(G, rho, e);
+  double iT = 1.0 / T;
+  double ob = 1.0 - G.b * rho;
+  double p = rho * G.R * T / ob - G.a * rho * rho;
+  bool interior = (i0 >= 0 && i0 < G.n[0]) && (i1 >= 0 && i1 < G.n[1]) && (i2 >= 0 && i2 < G.n[2]);
+  if (interior && !admissible(G, rho, T)) raise_flag(flags, ESVDW_F_INADMISSIBLE);
+  nd[F::RHO * G.PN + t] = rho;
+#pragma unroll
+  for (int m = 0; m < D; ++m) nd[(long)(F::V + m) * G.PN + t] = v[m];
+  nd[F::T * G.PN + t] = T;
+  nd[F::P * G.PN + t] = p;
+  nd[F::IT * G.PN + t] = iT;
+  nd[F::GG * G.PN + t] = G.R / ob - G.a * rho * iT;
+  // entropy variables: V = (-s + (e + p/rho - |v|^2/2)/T, v/T, -1/T), s = c_v ln T + R ln(1/rho - b)
+  double sent = G.cv * log(T) + G.R * log(ob / rho);
+  nd[(long)F::VS * G.PN + t] = -sent + (e + p / rho - 0.5 * v2) * iT;
+#pragma unroll
+  for (int m = 0; m < D; ++m) nd[(long)(F::VS + 1 + m) * G.PN + t] = v[m] * iT;
+  nd[(long)(F::VS + D + 1) * G.PN + t] = -iT;
+  // metrics
+  if (met_in) {
+    unsigned mir;
+    long ms = ghost_metric_src(G, i0, i1, i2, mir);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        double sg = 1.0;
+        for (int q = 0; q < D; ++q)
+          if ((mir >> q) & 1u)
+            if ((k == q) != (j == q)) sg = -sg;
+        nd[(long)(F::MS + k * D + j) * G.PN + t] = sg * met_in[(long)(k * D + j) * G.N + ms];
+      }
+      double xv = 0.0;
+      if (xit_in) {
+        double sg = ((mir >> k) & 1u) ? -1.0 : 1.0;
+        xv = sg * xit_in[(long)k * G.N + ms];
+      }
+      nd[(long)(F::XS + k) * G.PN + t] = xv;
+    }
+  } else {
+    double m[D][D];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        m[k][j] = metric_at<D>(G, xn, xd, cdt, dp, dpN, k, j, i0, i1, i2);
+        nd[(long)(F::MS + k * D + j) * G.PN + t] = m[k][j];
+      }
+    double xv[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) xv[j] = xd ? mesh_at(G, xd, j, i0, i1, i2, 1) : 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      double s2 = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) s2 -= xv[j] * m[k][j];
+      nd[(long)(F::XS + k) * G.PN + t] = s2;
+    }
+  }
+}
+
+// =============================== interface fluxes ================================
+
+template <int D> struct Nq {
+  double rho, v[D], T, p, iT, g, V[D + 2], m[D], mt;
+};
+
+template <int D, int K>
+__device__ __forceinline__ void load_node(const Geo &G, const double *__restrict__ nd, long t, Nq<D> &q) {
+  using F = NF_<D>;
+  q.rho = nd[F::RHO * G.PN + t];
+#pragma unroll
+  for (int m = 0; m < D; ++m) q.v[m] = nd[(long)(F::V + m) * G.PN + t];
+  q.T = nd[F::T * G.PN + t];
+  q.p = nd[F::P * G.PN + t];
+  q.iT = nd[F::IT * G.PN + t];
+  q.g = nd[F::GG * G.PN + t];
+#pragma unroll
+  for (int m = 0; m < D + 2; ++m) q.V[m] = nd[(long)(F::VS + m) * G.PN + t];
+#pragma unroll
+  for (int j = 0; j < D; ++j) q.m[j] = nd[(long)(F::MS + K * D + j) * G.PN + t];
+  q.mt = nd[(long)(F::XS + K) * G.PN + t];
+}
+
+// Two-point EC flux (eq. ECfluxMM with the closed-form U~, F~_j of Section 3.1), written in
+// contracted form: with the pair-averaged metrics mb, mbt and u = mbt + mb.v per node,
+//   F_rho = ({rho u} A + {g}{u})/D,  F_v = {v} F_rho + mb {rho}{T}{g},
+//   F_E = ({v/T}.F_v - K F_rho + a {rho u}{rho/T})/{1/T},
+// D = R/L(rho) + R b/L(1 - b rho) + R b/Pi - 2a/{T}, A = R b/Pi - a/{T},
+// K = {|v|^2/T}/2 - c_v {T}/L(T) + 2a{rho/T}.  Accumulates alpha*flux into acc and
+// alpha*{J dxi/dt} into gt.
+template <int D>
+__device__ __forceinline__ void ec_pair_acc(const Geo &G, const Nq<D> &l, const Nq<D> &r, double al,
+                                            double *acc, double &gt, unsigned &bad) {
+  double mb[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) mb[j] = 0.5 * (l.m[j] + r.m[j]);
+  double mbt = 0.5 * (l.mt + r.mt);
+  double ul = mbt, ur = mbt;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    ul += mb[j] * l.v[j];
+    ur += mb[j] * r.v[j];
+  }
+  double rhom = 0.5 * (l.rho + r.rho), Tm = 0.5 * (l.T + r.T), iTm = 0.5 * (l.iT + r.iT);
+  double rTm = 0.5 * (l.rho * l.iT + r.rho * r.iT), gm = 0.5 * (l.g + r.g);
+  double rum = 0.5 * (l.rho * ul + r.rho * ur), um = 0.5 * (ul + ur);
+  double obl = 1.0 - G.b * l.rho, obr = 1.0 - G.b * r.rho;
+  double Rb_Pi = G.R * G.b / (obl * obr);
+  double iTmean = 1.0 / Tm;
+  double Dd = G.R / logmean(l.rho, r.rho) + Rb_Pi - 2.0 * G.a * iTmean;
+  if (G.b > 0.0) Dd += G.R * G.b / logmean(obl, obr);
+  double A = Rb_Pi - G.a * iTmean;
+  double v2T = 0.0;
+#pragma unroll
+  for (int m = 0; m < D; ++m) v2T += l.v[m] * l.v[m] * l.iT + r.v[m] * r.v[m] * r.iT;
+  double Kk = 0.25 * v2T - G.cv * Tm / logmean(l.T, r.T) + 2.0 * G.a * rTm;
+  if (!(Dd > 0.0)) bad = 1u;
+  double Fr = (rum * A + gm * um) / Dd;
+  double pt = rhom * Tm * gm;
+  double sum = 0.0;
+#pragma unroll
+  for (int m = 0; m < D; ++m) {
+    double vm = 0.5 * (l.v[m] + r.v[m]);
+    double Fv = vm * Fr + mb[m] * pt;
+    acc[1 + m] += al * Fv;
+    sum += 0.5 * (l.v[m] * l.iT + r.v[m] * r.iT) * Fv;
+  }
+  acc[0] += al * Fr;
+  acc[D + 1] += al * (sum - Kk * Fr + G.a * rum * rTm) / iTm;
+  gt += al * mbt;
+}
+
+// scaled entropy variables W = R^T T V at one node for the interface eigen-system
+template <int D> struct Eig {
+  double n[D], tg[D - 1 > 0 ? D - 1 : 1][D];  // normal and tangent rows of the rotation
+  double un, ut[D > 1 ? D - 1 : 1], H, c, c2G, s0, s1, st;
+};
+
+template <int D>
+__device__ __forceinline__ void w_of(const Eig<D> &E, const double *V, double *W) {
+  // rotate the velocity part of V
+  double vn = 0.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) vn += E.n[j] * V[1 + j];
+  double vt[D > 1 ? D - 1 : 1];
+#pragma unroll
+  for (int t = 0; t < D - 1; ++t) {
+    vt[t] = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) vt[t] += E.tg[t][j] * V[1 + j];
+  }
+  double VE = V[D + 1];
+  double base = V[0] + E.un * vn + E.H * VE;
+#pragma unroll
+  for (int t = 0; t < D - 1; ++t) base += E.ut[t] * vt[t];
+  double ac = E.c * (vn + E.un * VE);
+  W[0] = E.s0 * (base - ac);
+  W[1] = E.s1 * (base - E.c2G * VE);
+#pragma unroll
+  for (int t = 0; t < D - 1; ++t) W[2 + t] = E.st * (vt[t] + E.ut[t] * VE);
+  W[D + 1] = E.s0 * (base + ac);
+}
+
+// magnitudes |R|^T |T V| of the terms summed into each W component (rounding scale of W)
+template <int D>
+__device__ __forceinline__ void wmag_of(const Eig<D> &E, const double *V, double *A) {
+  double vn = 0.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) vn += E.n[j] * V[1 + j];
+  double avt = 0.0, vt[D > 1 ? D - 1 : 1];
+#pragma unroll
+  for (int t = 0; t < D - 1; ++t) {
+    vt[t] = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) vt[t] += E.tg[t][j] * V[1 + j];
+    avt += fabs(E.ut[t]) * fabs(vt[t]);
+  }
+  double a0 = fabs(V[0]), an = fabs(vn), aE = fabs(V[D + 1]);
+  A[0] = E.s0 * (a0 + fabs(E.un - E.c) * an + avt + fabs(E.H - E.un * E.c) * aE);
+  A[1] = E.s1 * (a0 + fabs(E.un) * an + avt + fabs(E.H - E.c2G) * aE);
+#pragma unroll
+  for (int t = 0; t < D - 1; ++t) A[2 + t] = E.st * (fabs(vt[t]) + fabs(E.ut[t]) * aE);
+  A[D + 1] = E.s0 * (a0 + fabs(E.un + E.c) * an + avt + fabs(E.H + E.un * E.c) * aE);
+}
+
+template <int D, int K>
+__global__ void k_flux(Geo G, const double *__restrict__ nd, double *__restrict__ Fo, long nif, unsigned *flags) {
+  constexpr int NV = D + 2;
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= nif) return;
+  // interface index: direction K runs over -1 .. n_K - 1, the others over the interior
+  int e0 = G.n[0] + (K == 0), e1 = G.n[1] + (K == 1);
+  int a0 = (int)(t % e0), a1 = (int)((t / e0) % e1), a2 = (int)(t / ((long)e0 * e1));
+  int i0 = a0 - (K == 0), i1 = a1 - (K == 1), i2 = a2 - (K == 2);
+  // padded index of node (i - 2) along K and the stride along K
+  long base = ((long)(i2 + G.g[2]) * G.P[1] + (i1 + G.g[1])) * G.P[0] + (i0 + G.g[0]);
+  long stride = K == 0 ? 1 : (K == 1 ? (long)G.P[0] : (long)G.P[0] * G.P[1]);
+  Nq<D> q[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) load_node<D, K>(G, nd, base + (s - 2) * stride, q[s]);
+
+  double F[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) F[c] = 0.0;
+  double gt = 0.0;
+  unsigned bad = 0;
+  // eq. ECFlux_curv_2p: sum_m alpha_m sum_{s<m} F(i - s, i - s + m); node i is q[2]
+  ec_pair_acc<D>(G, q[2], q[3], AL1, F, gt, bad);
+  ec_pair_acc<D>(G, q[2], q[4], AL2, F, gt, bad);
+  ec_pair_acc<D>(G, q[1], q[3], AL2, F, gt, bad);
+  ec_pair_acc<D>(G, q[2], q[5], AL3, F, gt, bad);
+  ec_pair_acc<D>(G, q[1], q[4], AL3, F, gt, bad);
+  ec_pair_acc<D>(G, q[0], q[3], AL3, F, gt, bad);
+
+  if (G.diss) {
+    // averaged state at the interface
+    double rb = logmean(q[2].rho, q[3].rho);
+    double pb = rb / logmean(q[2].rho / q[2].p, q[3].rho / q[3].p);
+    double vb[D];
+#pragma unroll
+    for (int m = 0; m < D; ++m) vb[m] = 0.5 * (q[2].v[m] + q[3].v[m]);
+    double Tb = eos_T_rho_p(G, rb, pb);
+    double ob = 1.0 - G.b * rb;
+    double c2 = (1.0 + G.delta) * G.R * Tb / (ob * ob) - 2.0 * G.a * rb;
+    double mm[D], L2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      mm[j] = 0.5 * (q[2].m[j] + q[3].m[j]);
+      L2 += mm[j] * mm[j];
+    }
+    double mtb = 0.5 * (q[2].mt + q[3].mt);
+    double L = sqrt(L2);
+    Eig<D> E;
+#pragma unroll
+    for (int j = 0; j < D; ++j) E.n[j] = mm[j] / L;
+    if constexpr (D == 2) {
+      E.tg[0][0] = -E.n[1];
+      E.tg[0][1] = E.n[0];
+    } else if constexpr (D == 3) {
+      double sxy = sqrt(E.n[0] * E.n[0] + E.n[1] * E.n[1]);
+      double ct = 1.0, st = 0.0;
+      if (sxy > 0.0) {
+        ct = E.n[0] / sxy;
+        st = E.n[1] / sxy;
+      }
+      E.tg[0][0] = -st;
+      E.tg[0][1] = ct;
+      E.tg[0][2] = 0.0;
+      E.tg[1][0] = -E.n[2] * ct;
+      E.tg[1][1] = -E.n[2] * st;
+      E.tg[1][2] = sxy;
+    }
+    double un = 0.0, vv = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      un += E.n[j] * vb[j];
+      vv += vb[j] * vb[j];
+    }
+    E.un = un;
+#pragma unroll
+    for (int t2 = 0; t2 < D - 1; ++t2) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) s += E.tg[t2][j] * vb[j];
+      E.ut[t2] = s;
+    }
+    double Eb = rb * (G.cv * Tb - G.a * rb) + 0.5 * rb * vv;
+    E.H = (Eb + pb) / rb;
+    E.c = sqrt(c2);
+    E.c2G = c2 * G.cv * ob / G.R;  // c^2 / Gamma with Gamma = R/(c_v (1 - b rho))
+    double ac = G.R * Tb - 2.0 * G.a * rb * ob * ob;
+    double S0 = rb * Tb / (2.0 * c2), S1 = G.R * G.R * rb * Tb * Tb / (G.cv * ac * c2), St = rb * Tb;
+    if (!(S0 > 0.0) || !(S1 > 0.0)) bad = 1u;
+    E.s0 = sqrt(fabs(S0));
+    E.s1 = sqrt(fabs(S1));
+    E.st = sqrt(fabs(St));
+    double Lam = fmax(fabs(mtb + L * (un - E.c)), fmax(fabs(mtb + L * un), fabs(mtb + L * (un + E.c))));
+    double W[6][NV];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) w_of<D>(E, q[s].V, W[s]);
+    double A2[NV], A3[NV];
+    wmag_of<D>(E, q[2].V, A2);
+    wmag_of<D>(E, q[3].V, A3);
+    double y[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      double wm = mrweno5(G, W[0][c], W[1][c], W[2][c], W[3][c], W[4][c]);
+      double wp = mrweno5(G, W[5][c], W[4][c], W[3][c], W[2][c], W[1][c]);
+      double jr = wp - wm, j0 = W[3][c] - W[2][c];
+      // a plain jump below the rounding scale of W (2^-40 of its terms) counts as zero
+      if (fabs(j0) <= ldexp(A2[c] + A3[c], -40)) j0 = 0.0;
+      y[c] = ((jr > 0.0 && j0 > 0.0) || (jr < 0.0 && j0 < 0.0)) ? jr : 0.0;
+    }
+    // R y in the rotated frame, then rotate the momentum back (T^T)
+    double a0 = E.s0 * y[0], a1 = E.s1 * y[1], a2 = E.s0 * y[D + 1];
+    double dr = a0 + a1 + a2;
+    double dn = a0 * (un - E.c) + a1 * un + a2 * (un + E.c);
+    double dE = a0 * (E.H - un * E.c) + a1 * (E.H - E.c2G) + a2 * (E.H + un * E.c);
+    double dt_[D > 1 ? D - 1 : 1];
+#pragma unroll
+    for (int t2 = 0; t2 < D - 1; ++t2) {
+      dt_[t2] = E.ut[t2] * dr + E.st * y[2 + t2];
+      dE += E.st * y[2 + t2] * E.ut[t2];
+    }
+    double h = 0.5 * Lam;
+    F[0] -= h * dr;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      double mj = E.n[j] * dn;
+#pragma unroll
+      for (int t2 = 0; t2 < D - 1; ++t2) mj += E.tg[t2][j] * dt_[t2];
+      F[1 + j] -= h * mj;
+    }
+    F[D + 1] -= h * dE;
+  }
+  if (bad) raise_flag(flags, ESVDW_F_MEANCONSTRAINT);
+#pragma unroll
+  for (int c = 0; c < NV; ++c) Fo[(long)c * nif + t] = F[c];
+  Fo[(long)NV * nif + t] = gt;
+}
+
+// =============================== update ==========================================
+
+// mode 0: write dJU, dJ.  mode 1: SSP-RK3 stage s combination with dt from the device.
+template <int D>
+__global__ void k_update(Geo G, const double *__restrict__ F0, const double *__restrict__ F1,
+                         const double *__restrict__ F2, long nif0, long nif1, long nif2, int mode, int s,
+                         const double *__restrict__ dtp, const double *__restrict__ base_JU,
+                         const double *__restrict__ base_J, const double *__restrict__ in_JU,
+                         const double *__restrict__ in_J, double *__restrict__ out_JU, double *__restrict__ out_J,
+                         unsigned *flags) {
+  constexpr int NV = D + 2;
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= G.N) return;
+  int i0 = (int)(t % G.n[0]), i1 = (int)((t / G.n[0]) % G.n[1]), i2 = (int)(t / ((long)G.n[0] * G.n[1]));
+  double L[NV + 1];
+#pragma unroll
+  for (int c = 0; c <= NV; ++c) L[c] = 0.0;
+  {  // direction 0: interfaces (i0 - 1/2) at a0 = i0 and (i0 + 1/2) at a0 = i0 + 1
+    long r = ((long)i2 * G.n[1] + i1) * (G.n[0] + 1) + i0;
+#pragma unroll
+    for (int c = 0; c <= NV; ++c) L[c] += (F0[(long)c * nif0 + r] - F0[(long)c * nif0 + r + 1]) * G.idxi[0];
+  }
+  if (D > 1) {
+    long r = ((long)i2 * (G.n[1] + 1) + i1) * G.n[0] + i0;
+#pragma unroll
+    for (int c = 0; c <= NV; ++c) L[c] += (F1[(long)c * nif1 + r] - F1[(long)c * nif1 + r + G.n[0]]) * G.idxi[1];
+  }
+  if (D > 2) {
+    long r = ((long)i2 * G.n[1] + i1) * G.n[0] + i0;
+    long st = (long)G.n[0] * G.n[1];
+#pragma unroll
+    for (int c = 0; c <= NV; ++c) L[c] += (F2[(long)c * nif2 + r] - F2[(long)c * nif2 + r + st]) * G.idxi[2];
+  }
+  bool nan = false;
+  if (mode == 0) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      out_JU[(long)c * G.N + t] = L[c];
+      nan |= isnan(L[c]);
+    }
+    out_J[t] = L[NV];
+    nan |= isnan(L[NV]);
+  } else {
+    double dt = *dtp;
+#pragma unroll
+    for (int c = 0; c <= NV; ++c) {
+      const double *inp = c < NV ? in_JU + (long)c * G.N : in_J;
+      const double *bp = c < NV ? base_JU + (long)c * G.N : base_J;
+      double y = inp[t] + dt * L[c];
+      double o;
+      if (s == 0) o = y;
+      else if (s == 1) o = 0.75 * bp[t] + 0.25 * y;
+      else o = (1.0 / 3.0) * bp[t] + (2.0 / 3.0) * y;
+      nan |= isnan(o);
+      if (c < NV) out_JU[(long)c * G.N + t] = o;
+      else out_J[t] = o;
+    }
+  }
+  if (nan) raise_flag(flags, ESVDW_F_NAN);
+  (void)i0;
+}
+
+// =============================== small kernels ===================================
+
+__global__ void k_uniform_mesh(Geo G, double *__restrict__ x) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= G.N) return;
+  int ii[3] = {(int)(t % G.n[0]), (int)((t / G.n[0]) % G.n[1]), (int)(t / ((long)G.n[0] * G.n[1]))};
+  for (int j = 0; j < G.dim; ++j) x[(long)j * G.N + t] = G.lo[j] + (ii[j] + 0.5) * G.dxi[j];
+}
+
+template <int D>
+__global__ void k_init_state(Geo G, const double *__restrict__ prim, const double *__restrict__ J,
+                             double *__restrict__ JU) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= G.N) return;
+  double rho = prim[t], p = prim[(long)(D + 1) * G.N + t];
+  double T = eos_T_rho_p(G, rho, p);
+  double jj = J[t], v2 = 0.0;
+  JU[t] = jj * rho;
+  for (int m = 0; m < D; ++m) {
+    double v = prim[(long)(1 + m) * G.N + t];
+    v2 += v * v;
+    JU[(long)(1 + m) * G.N + t] = jj * rho * v;
+  }
+  JU[(long)(D + 1) * G.N + t] = jj * (rho * (G.cv * T - G.a * rho) + 0.5 * rho * v2);
+}
+
+__global__ void k_axpy_mesh(long n, const double *__restrict__ x, const double *__restrict__ xd,
+                            const double *__restrict__ dtp, double f, double *out) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  out[t] = x[t] + f * (*dtp) * xd[t];
+}
+
+// =============================== launchers =======================================
+
+static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+int launch_dprod(esvdw_ctx *c, const double *xn, const double *xd, double cdt, hipStream_t st) {
+  if (c->G.dim != 3) return 0;
+  hipLaunchKernelGGL(k_dprod, dim3(nblk(c->dpN, 256)), dim3(256), 0, st, c->G, xn, xd, cdt, c->dprod, c->dpN);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_metrics(esvdw_ctx *c, const double *x, const double *xd, double *met, double *xit, double *J,
+                   hipStream_t st) {
+  const Geo &G = c->G;
+  if (launch_dprod(c, x, nullptr, 0.0, st)) return -1;
+  dim3 b(256), g(nblk(G.N, 256));
+  if (G.dim == 1) hipLaunchKernelGGL(k_metrics<1>, g, b, 0, st, G, x, xd, c->dprod, c->dpN, met, xit, J);
+  else if (G.dim == 2) hipLaunchKernelGGL(k_metrics<2>, g, b, 0, st, G, x, xd, c->dprod, c->dpN, met, xit, J);
+  else hipLaunchKernelGGL(k_metrics<3>, g, b, 0, st, G, x, xd, c->dprod, c->dpN, met, xit, J);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int D>
+static int rhs_pipeline_d(esvdw_ctx *c, const double *JU, const double *J, const double *met, const double *xit,
+                          const double *xn, const double *xd, double cdt, int mode, int s, const double *dtp,
+                          const double *bJU, const double *bJ, double *oJU, double *oJ, hipStream_t st) {
+  const Geo &G = c->G;
+  if (!met && D == 3)
+    if (launch_dprod(c, xn, xd, cdt, st)) return -1;
+  hipLaunchKernelGGL(k_nodes<D>, dim3(nblk(G.PN, 256)), dim3(256), 0, st, G, JU, J, met, xit, xn, xd, cdt, c->dprod,
+                     c->dpN, c->node, c->flags);
+  constexpr int K1 = D > 1 ? 1 : 0, K2 = D > 2 ? 2 : 0;
+  hipLaunchKernelGGL((k_flux<D, 0>), dim3(nblk(c->nif[0], 128)), dim3(128), 0, st, G, c->node, c->flux[0], c->nif[0],
+                     c->flags);
+  if (D > 1)
+    hipLaunchKernelGGL((k_flux<D, K1>), dim3(nblk(c->nif[1], 128)), dim3(128), 0, st, G, c->node, c->flux[1],
+                       c->nif[1], c->flags);
+  if (D > 2)
+    hipLaunchKernelGGL((k_flux<D, K2>), dim3(nblk(c->nif[2], 128)), dim3(128), 0, st, G, c->node, c->flux[2],
+                       c->nif[2], c->flags);
+  hipLaunchKernelGGL(k_update<D>, dim3(nblk(G.N, 256)), dim3(256), 0, st, G, c->flux[0], c->flux[1], c->flux[2],
+                     c->nif[0], c->nif[1], c->nif[2], mode, s, dtp, bJU, bJ, JU, J, oJU, oJ, c->flags);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_rhs(esvdw_ctx *c, const double *JU, const double *J, const double *met, const double *xit,
+               const double *xn, const double *xd, double cdt, int mode, int s, const double *dtp,
+               const double *bJU, const double *bJ, double *oJU, double *oJ, hipStream_t st) {
+  switch (c->G.dim) {
+    case 1: return rhs_pipeline_d<1>(c, JU, J, met, xit, xn, xd, cdt, mode, s, dtp, bJU, bJ, oJU, oJ, st);
+    case 2: return rhs_pipeline_d<2>(c, JU, J, met, xit, xn, xd, cdt, mode, s, dtp, bJU, bJ, oJU, oJ, st);
+    default: return rhs_pipeline_d<3>(c, JU, J, met, xit, xn, xd, cdt, mode, s, dtp, bJU, bJ, oJU, oJ, st);
+  }
+}
+
+int launch_uniform_mesh(esvdw_ctx *c, double *x, hipStream_t st) {
+  hipLaunchKernelGGL(k_uniform_mesh, dim3(nblk(c->G.N, 256)), dim3(256), 0, st, c->G, x);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_init_state(esvdw_ctx *c, const double *prim, const double *J, double *JU, hipStream_t st) {
+  dim3 b(256), g(nblk(c->G.N, 256));
+  if (c->G.dim == 1) hipLaunchKernelGGL(k_init_state<1>, g, b, 0, st, c->G, prim, J, JU);
+  else if (c->G.dim == 2) hipLaunchKernelGGL(k_init_state<2>, g, b, 0, st, c->G, prim, J, JU);
+  else hipLaunchKernelGGL(k_init_state<3>, g, b, 0, st, c->G, prim, J, JU);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_axpy_mesh(esvdw_ctx *c, const double *x, const double *xd, const double *dtp, double f, double *out,
+                     hipStream_t st) {
+  long n = (long)c->G.dim * c->G.N;
+  hipLaunchKernelGGL(k_axpy_mesh, dim3(nblk(n, 256)), dim3(256), 0, st, n, x, xd, dtp, f, out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
