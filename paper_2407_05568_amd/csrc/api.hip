@@ -93,7 +93,7 @@ int esvdw_create(const esvdw_params *p, esvdw_ctx **out) {
   (void)hipGetDevice(&c->dev);
   const Geo &G = c->G;
   int D = G.dim, nv = G.nv;
-  c->NF = 2 * D + 7 + D * D;
+  c->NF = D == 1 ? NF_<1>::COUNT : (D == 2 ? NF_<2>::COUNT : NF_<3>::COUNT);
   long N = G.N;
   bool ok = dalloc(&c->node, (size_t)c->NF * G.PN);
   for (int k = 0; k < 3; ++k) {
