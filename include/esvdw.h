@@ -151,6 +151,14 @@ int cfl_dt(esvdw_ctx *ctx, const double *JU, const double *J, const double *x, d
 int esvdw_step(esvdw_ctx *ctx, double *JU, double *J, double *x, int moving, double *dt_dev,
                hipStream_t stream);
 
+/* Measurement hook: launches one internal kernel `reps` times on `stream` with the
+ * context's current scratch contents, so that a caller can bracket it with stream events.
+ * which = 1, 2, 3: the interface-flux kernel of direction 1, 2, 3 (reads the node data left
+ * by the last RHS evaluation, writes the context's flux buffer); which = 5: one Jacobi sweep
+ * of the context's mesh-iteration buffers.  Call only after a step or RHS on this context.
+ * EINVAL for an unknown kernel or a direction beyond dim. */
+int esvdw_bench_kernel(esvdw_ctx *ctx, int which, int reps, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -48,10 +48,12 @@ static void make_geo(const esvdw_params *p, Geo *G) {
   G->a = p->a;
   G->b = p->b;
   G->delta = p->R / p->cv;
+  G->iR = 1.0 / p->R;
   G->wl0 = p->weno_lin[0];
   G->wl1 = p->weno_lin[1];
   G->wl2 = p->weno_lin[2];
   G->weps = p->weno_eps;
+  G->iwl0 = 1.0 / p->weno_lin[0];
   G->diss = p->dissipation;
 }
 
@@ -254,6 +256,22 @@ int esvdw_step(esvdw_ctx *c, double *JU, double *J, double *x, int moving, doubl
   if (!r) r = rk_stage(c, 1, dt_dev, JU, J, aU, aJ, x, xd, bU, bJ, nullptr, st);
   if (!r) r = rk_stage(c, 2, dt_dev, JU, J, bU, bJ, x, xd, JU, J, moving ? x : nullptr, st);
   return r;
+}
+
+int esvdw_bench_kernel(esvdw_ctx *c, int which, int reps, hipStream_t st) {
+  if (!c || reps < 0) return ESVDW_EINVAL;
+  if (which >= 1 && which <= 3) {
+    if (which > c->G.dim) return ESVDW_EINVAL;
+    for (int r = 0; r < reps; ++r)
+      if (launch_flux_only(c, which - 1, st)) return ESVDW_EHIP;
+    return ESVDW_OK;
+  }
+  if (which == 5) {
+    for (int r = 0; r < reps; ++r)
+      if (launch_jacobi(c, c->omega, c->xmu, 1, nullptr, st)) return ESVDW_EHIP;
+    return ESVDW_OK;
+  }
+  return ESVDW_EINVAL;
 }
 
 }  // extern "C"

@@ -20,8 +20,8 @@ struct Geo {
   long N, PN;  // interior / padded node counts
   double lo[3], hi[3], dxi[3], idxi[3], period[3];
   int bc[3];
-  double R, cv, a, b, delta;
-  double wl0, wl1, wl2, weps;
+  double R, cv, a, b, delta, iR;
+  double wl0, wl1, wl2, weps, iwl0;
   int diss;
 };
 
@@ -44,6 +44,8 @@ __device__ __forceinline__ long lin(const Geo &G, int i0, int i1, int i2) {
 }
 
 __device__ __forceinline__ long state_index(const Geo &G, int i0, int i1, int i2) {
+  if ((unsigned)i0 < (unsigned)G.n[0] && (unsigned)i1 < (unsigned)G.n[1] && (unsigned)i2 < (unsigned)G.n[2])
+    return lin(G, i0, i1, i2);
   return lin(G, state_src(i0, G.n[0], G.bc[0]), state_src(i1, G.n[1], G.bc[1]), state_src(i2, G.n[2], G.bc[2]));
 }
 
@@ -53,6 +55,8 @@ __device__ __forceinline__ long state_index(const Geo &G, int i0, int i1, int i2
 // the others even).  vel != 0: a mesh velocity component (no shift, same parity).
 __device__ __forceinline__ double mesh_at(const Geo &G, const double *__restrict__ x, int j, int i0, int i1,
                                           int i2, int vel) {
+  if ((unsigned)i0 < (unsigned)G.n[0] && (unsigned)i1 < (unsigned)G.n[1] && (unsigned)i2 < (unsigned)G.n[2])
+    return x[(long)j * G.N + lin(G, i0, i1, i2)];
   int ii[3] = {i0, i1, i2};
   double sg = 1.0, off = 0.0;
 #pragma unroll
@@ -116,6 +120,22 @@ __device__ __forceinline__ double logmean(double al, double ar) {
   return 0.5 * s / h;
 }
 
+// 1/L(a_l, a_r) for the logarithmic mean L = (a_r - a_l)/(ln a_r - ln a_l), given the node
+// logarithms la = ln a_l, lb = ln a_r.  Close arguments (|a_r - a_l| < 0.1 (a_l + a_r), i.e.
+// f = (a_r - a_l)/(a_r + a_l) with f^2 < 0.01) use 1/L = 2 (atanh(f)/f)/(a_l + a_r) with
+// the Taylor series of atanh(f)/f to u^8 (truncation < 1e-17); otherwise the logarithms.
+__device__ __forceinline__ double inv_logmean(double al, double ar, double la, double lb) {
+  double d = ar - al, s = al + ar;
+  if (fabs(d) < 0.1 * s) {
+    double is = 1.0 / s;
+    double f = d * is, u = f * f;
+    double h = 1.0 + u * (1.0 / 3 + u * (1.0 / 5 + u * (1.0 / 7 + u * (1.0 / 9 + u * (1.0 / 11 + u * (1.0 / 13 +
+               u * (1.0 / 15 + u * (1.0 / 17))))))));
+    return 2.0 * h * is;
+  }
+  return (lb - la) / d;
+}
+
 // Multi-resolution WENO, fifth order: left limit at the right face of the centre cell of
 // (a, b, c, d, e) = w_{i-2..i+2}.  Hierarchy of central levels: 1 point (w_i), 3 points
 // (quadratic), 5 points (quartic) with linear weights wl2, wl1, wl0.
@@ -133,12 +153,14 @@ __device__ __forceinline__ double mrweno5(const Geo &G, double a, double b, doub
               (1.0 / 5040.0);
   double tt = 0.5 * (fabs(s5 - s1) + fabs(s5 - s3));
   double tau = tt * tt;
-  double w5 = G.wl0 * (1.0 + tau / (s5 + G.weps));
-  double w3 = G.wl1 * (1.0 + tau / (s3 + G.weps));
-  double w1 = G.wl2 * (1.0 + tau / (s1 + G.weps));
-  double inv = 1.0 / (w5 + w3 + w1);
-  double top = (q5 - G.wl1 * q3 - G.wl2 * c) / G.wl0;
-  return (w5 * top + w3 * q3 + w1 * c) * inv;
+  // w_l = wl_l (1 + tau/(s_l + eps)), normalised; multiplied through by the product of the
+  // (s_l + eps) so that one division remains
+  double e5 = s5 + G.weps, e3 = s3 + G.weps, e1 = s1 + G.weps;
+  double w5 = G.wl0 * (e3 * e1) * (e5 + tau);
+  double w3 = G.wl1 * (e5 * e1) * (e3 + tau);
+  double w1 = G.wl2 * (e5 * e3) * (e1 + tau);
+  double top = (q5 - G.wl1 * q3 - G.wl2 * c) * G.iwl0;
+  return (w5 * top + w3 * q3 + w1 * c) / (w5 + w3 + w1);
 }
 
 // ---------------------------------------------------------------------------------
@@ -211,8 +233,11 @@ struct esvdw_ctx {
   unsigned *flags;
 };
 
-// node-buffer field offsets for dimension D
+// node-buffer field offsets for dimension D: primitives, 1/T, g = R/(1 - b rho) - a rho/T,
+// 1/(1 - b rho), the logarithms of rho, 1 - b rho, T, p, the entropy variables, the metrics
+// J dxi_k/dx_j and J dxi_k/dt
 template <int D> struct NF_ {
-  static constexpr int RHO = 0, V = 1, T = D + 1, P = D + 2, IT = D + 3, GG = D + 4, VS = D + 5, MS = VS + D + 2,
-                       XS = MS + D * D, COUNT = XS + D;
+  static constexpr int RHO = 0, V = 1, T = D + 1, P = D + 2, IT = D + 3, GG = D + 4, IOB = D + 5, LNR = D + 6,
+                       LNB = D + 7, LNT = D + 8, LNP = D + 9, VS = D + 10, MS = VS + D + 2, XS = MS + D * D,
+                       COUNT = XS + D;
 };

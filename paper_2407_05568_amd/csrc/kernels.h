@@ -23,3 +23,4 @@ int launch_xdot(esvdw_ctx *c, const double *xn, const double *xmu, const double 
                 hipStream_t st);
 int launch_copy(const double *src, double *dst, long n, hipStream_t st);
 int launch_add(const double *a, const double *b, double *dst, long n, hipStream_t st);
+int launch_flux_only(esvdw_ctx *c, int K, hipStream_t st);

@@ -153,29 +153,37 @@ __global__ void k_nodes(Geo G, const double *__restrict__ JU, const double *__re
   long s = state_index(G, i0, i1, i2);
   double iJ = 1.0 / J[s];
   double rho = JU[s] * iJ;
+  double irho = 1.0 / rho;
   double v[D], v2 = 0.0;
 #pragma unroll
   for (int m = 0; m < D; ++m) {
-    v[m] = JU[(long)(1 + m) * G.N + s] * iJ / rho;
+    v[m] = JU[(long)(1 + m) * G.N + s] * iJ * irho;
     v2 += v[m] * v[m];
   }
-  double e = JU[(long)(D + 1) * G.N + s] * iJ / rho - 0.5 * v2;
-  double T = eos_T_rho_e(G, rho, e);
+  double e = JU[(long)(D + 1) * G.N + s] * iJ * irho - 0.5 * v2;
+  double T = (e + G.a * rho) / G.cv;
   double iT = 1.0 / T;
   double ob = 1.0 - G.b * rho;
-  double p = rho * G.R * T / ob - G.a * rho * rho;
+  double iob = 1.0 / ob;
+  double p = rho * G.R * T * iob - G.a * rho * rho;
   bool interior = (i0 >= 0 && i0 < G.n[0]) && (i1 >= 0 && i1 < G.n[1]) && (i2 >= 0 && i2 < G.n[2]);
   if (interior && !admissible(G, rho, T)) raise_flag(flags, ESVDW_F_INADMISSIBLE);
+  double lnr = log(rho), lnb = log(ob), lnt = log(T), lnp = log(p);
   nd[F::RHO * G.PN + t] = rho;
 #pragma unroll
   for (int m = 0; m < D; ++m) nd[(long)(F::V + m) * G.PN + t] = v[m];
   nd[F::T * G.PN + t] = T;
   nd[F::P * G.PN + t] = p;
   nd[F::IT * G.PN + t] = iT;
-  nd[F::GG * G.PN + t] = G.R / ob - G.a * rho * iT;
+  nd[F::GG * G.PN + t] = G.R * iob - G.a * rho * iT;
+  nd[F::IOB * G.PN + t] = iob;
+  nd[F::LNR * G.PN + t] = lnr;
+  nd[F::LNB * G.PN + t] = lnb;
+  nd[F::LNT * G.PN + t] = lnt;
+  nd[F::LNP * G.PN + t] = lnp;
   // entropy variables: V = (-s + (e + p/rho - |v|^2/2)/T, v/T, -1/T), s = c_v ln T + R ln(1/rho - b)
-  double sent = G.cv * log(T) + G.R * log(ob / rho);
-  nd[(long)F::VS * G.PN + t] = -sent + (e + p / rho - 0.5 * v2) * iT;
+  double sent = G.cv * lnt + G.R * (lnb - lnr);
+  nd[(long)F::VS * G.PN + t] = -sent + (e + p * irho - 0.5 * v2) * iT;
 #pragma unroll
   for (int m = 0; m < D; ++m) nd[(long)(F::VS + 1 + m) * G.PN + t] = v[m] * iT;
   nd[(long)(F::VS + D + 1) * G.PN + t] = -iT;
@@ -223,23 +231,39 @@ __global__ void k_nodes(Geo G, const double *__restrict__ JU, const double *__re
 }
 
 // =============================== interface fluxes ================================
+//
+// One block owns a tile of interfaces normal to direction K.  Phase 1: every node that
+// owns a pair flux used by the tile (the tile's nodes along K plus two more on the low
+// side) computes its three two-point fluxes F(i, i+m), m = 1, 2, 3, into LDS.  Phase 2:
+// each thread combines the six pair fluxes of its interface with alpha_m (eq.
+// ECFlux_curv_2p) and subtracts the dissipation of eq. HOstable.
 
-template <int D> struct Nq {
-  double rho, v[D], T, p, iT, g, V[D + 2], m[D], mt;
+template <int D, int K> struct Tile;
+template <> struct Tile<1, 0> { static constexpr int X = 256, Y = 1, Z = 1; };
+template <> struct Tile<2, 0> { static constexpr int X = 64, Y = 4, Z = 1; };
+template <> struct Tile<2, 1> { static constexpr int X = 16, Y = 16, Z = 1; };
+template <> struct Tile<3, 0> { static constexpr int X = 64, Y = 4, Z = 1; };
+template <> struct Tile<3, 1> { static constexpr int X = 16, Y = 16, Z = 1; };
+template <> struct Tile<3, 2> { static constexpr int X = 16, Y = 4, Z = 4; };
+
+// node data used by a pair flux (direction K)
+template <int D> struct Pq {
+  double rho, v[D], T, iT, g, iob, lr, lb, lt, m[D], mt;
 };
 
 template <int D, int K>
-__device__ __forceinline__ void load_node(const Geo &G, const double *__restrict__ nd, long t, Nq<D> &q) {
+__device__ __forceinline__ void load_pq(const Geo &G, const double *__restrict__ nd, long t, Pq<D> &q) {
   using F = NF_<D>;
   q.rho = nd[F::RHO * G.PN + t];
 #pragma unroll
   for (int m = 0; m < D; ++m) q.v[m] = nd[(long)(F::V + m) * G.PN + t];
   q.T = nd[F::T * G.PN + t];
-  q.p = nd[F::P * G.PN + t];
   q.iT = nd[F::IT * G.PN + t];
   q.g = nd[F::GG * G.PN + t];
-#pragma unroll
-  for (int m = 0; m < D + 2; ++m) q.V[m] = nd[(long)(F::VS + m) * G.PN + t];
+  q.iob = nd[F::IOB * G.PN + t];
+  q.lr = nd[F::LNR * G.PN + t];
+  q.lb = nd[F::LNB * G.PN + t];
+  q.lt = nd[F::LNT * G.PN + t];
 #pragma unroll
   for (int j = 0; j < D; ++j) q.m[j] = nd[(long)(F::MS + K * D + j) * G.PN + t];
   q.mt = nd[(long)(F::XS + K) * G.PN + t];
@@ -250,11 +274,9 @@ __device__ __forceinline__ void load_node(const Geo &G, const double *__restrict
 //   F_rho = ({rho u} A + {g}{u})/D,  F_v = {v} F_rho + mb {rho}{T}{g},
 //   F_E = ({v/T}.F_v - K F_rho + a {rho u}{rho/T})/{1/T},
 // D = R/L(rho) + R b/L(1 - b rho) + R b/Pi - 2a/{T}, A = R b/Pi - a/{T},
-// K = {|v|^2/T}/2 - c_v {T}/L(T) + 2a{rho/T}.  Accumulates alpha*flux into acc and
-// alpha*{J dxi/dt} into gt.
+// K = {|v|^2/T}/2 - c_v {T}/L(T) + 2a{rho/T}; out[nv] receives {J dxi/dt}.
 template <int D>
-__device__ __forceinline__ void ec_pair_acc(const Geo &G, const Nq<D> &l, const Nq<D> &r, double al,
-                                            double *acc, double &gt, unsigned &bad) {
+__device__ __forceinline__ void ec_pair(const Geo &G, const Pq<D> &l, const Pq<D> &r, double *out, unsigned &bad) {
   double mb[D];
 #pragma unroll
   for (int j = 0; j < D; ++j) mb[j] = 0.5 * (l.m[j] + r.m[j]);
@@ -268,41 +290,42 @@ __device__ __forceinline__ void ec_pair_acc(const Geo &G, const Nq<D> &l, const 
   double rhom = 0.5 * (l.rho + r.rho), Tm = 0.5 * (l.T + r.T), iTm = 0.5 * (l.iT + r.iT);
   double rTm = 0.5 * (l.rho * l.iT + r.rho * r.iT), gm = 0.5 * (l.g + r.g);
   double rum = 0.5 * (l.rho * ul + r.rho * ur), um = 0.5 * (ul + ur);
-  double obl = 1.0 - G.b * l.rho, obr = 1.0 - G.b * r.rho;
-  double Rb_Pi = G.R * G.b / (obl * obr);
-  double iTmean = 1.0 / Tm;
-  double Dd = G.R / logmean(l.rho, r.rho) + Rb_Pi - 2.0 * G.a * iTmean;
-  if (G.b > 0.0) Dd += G.R * G.b / logmean(obl, obr);
+  double Rb_Pi = G.R * G.b * l.iob * r.iob;
+  double iTmean = 2.0 / (l.T + r.T);
+  double Dd = G.R * inv_logmean(l.rho, r.rho, l.lr, r.lr) + Rb_Pi - 2.0 * G.a * iTmean;
+  if (G.b > 0.0) {
+    double obl = 1.0 - G.b * l.rho, obr = 1.0 - G.b * r.rho;
+    Dd += G.R * G.b * inv_logmean(obl, obr, l.lb, r.lb);
+  }
   double A = Rb_Pi - G.a * iTmean;
   double v2T = 0.0;
 #pragma unroll
   for (int m = 0; m < D; ++m) v2T += l.v[m] * l.v[m] * l.iT + r.v[m] * r.v[m] * r.iT;
-  double Kk = 0.25 * v2T - G.cv * Tm / logmean(l.T, r.T) + 2.0 * G.a * rTm;
+  double Kk = 0.25 * v2T - G.cv * Tm * inv_logmean(l.T, r.T, l.lt, r.lt) + 2.0 * G.a * rTm;
   if (!(Dd > 0.0)) bad = 1u;
   double Fr = (rum * A + gm * um) / Dd;
   double pt = rhom * Tm * gm;
   double sum = 0.0;
 #pragma unroll
   for (int m = 0; m < D; ++m) {
-    double vm = 0.5 * (l.v[m] + r.v[m]);
-    double Fv = vm * Fr + mb[m] * pt;
-    acc[1 + m] += al * Fv;
+    double Fv = 0.5 * (l.v[m] + r.v[m]) * Fr + mb[m] * pt;
+    out[1 + m] = Fv;
     sum += 0.5 * (l.v[m] * l.iT + r.v[m] * r.iT) * Fv;
   }
-  acc[0] += al * Fr;
-  acc[D + 1] += al * (sum - Kk * Fr + G.a * rum * rTm) / iTm;
-  gt += al * mbt;
+  out[0] = Fr;
+  out[D + 1] = (sum - Kk * Fr + G.a * rum * rTm) / iTm;
+  out[D + 2] = mbt;
 }
 
-// scaled entropy variables W = R^T T V at one node for the interface eigen-system
+// interface eigen-system in the rotated frame
 template <int D> struct Eig {
   double n[D], tg[D - 1 > 0 ? D - 1 : 1][D];  // normal and tangent rows of the rotation
   double un, ut[D > 1 ? D - 1 : 1], H, c, c2G, s0, s1, st;
 };
 
+// scaled entropy variables W = R^T T V at one node
 template <int D>
 __device__ __forceinline__ void w_of(const Eig<D> &E, const double *V, double *W) {
-  // rotate the velocity part of V
   double vn = 0.0;
 #pragma unroll
   for (int j = 0; j < D; ++j) vn += E.n[j] * V[1 + j];
@@ -348,55 +371,91 @@ __device__ __forceinline__ void wmag_of(const Eig<D> &E, const double *V, double
 }
 
 template <int D, int K>
-__global__ void k_flux(Geo G, const double *__restrict__ nd, double *__restrict__ Fo, long nif, unsigned *flags) {
-  constexpr int NV = D + 2;
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (t >= nif) return;
-  // interface index: direction K runs over -1 .. n_K - 1, the others over the interior
-  int e0 = G.n[0] + (K == 0), e1 = G.n[1] + (K == 1);
-  int a0 = (int)(t % e0), a1 = (int)((t / e0) % e1), a2 = (int)(t / ((long)e0 * e1));
-  int i0 = a0 - (K == 0), i1 = a1 - (K == 1), i2 = a2 - (K == 2);
-  // padded index of node (i - 2) along K and the stride along K
-  long base = ((long)(i2 + G.g[2]) * G.P[1] + (i1 + G.g[1])) * G.P[0] + (i0 + G.g[0]);
-  long stride = K == 0 ? 1 : (K == 1 ? (long)G.P[0] : (long)G.P[0] * G.P[1]);
-  Nq<D> q[6];
-#pragma unroll
-  for (int s = 0; s < 6; ++s) load_node<D, K>(G, nd, base + (s - 2) * stride, q[s]);
-
-  double F[NV];
-#pragma unroll
-  for (int c = 0; c < NV; ++c) F[c] = 0.0;
-  double gt = 0.0;
+__global__ void __launch_bounds__(256) k_flux(Geo G, const double *__restrict__ nd, double *__restrict__ Fo, long nif,
+                                              unsigned *flags) {
+  using F = NF_<D>;
+  using TL = Tile<D, K>;
+  constexpr int NV = D + 2, NC = NV + 1;
+  constexpr int QX = TL::X + 2 * (K == 0), QY = TL::Y + 2 * (K == 1), QZ = TL::Z + 2 * (K == 2);
+  constexpr int Q = QX * QY * QZ;
+  __shared__ double sP[NC * 3 * Q];
+  const int tid = threadIdx.x;
+  const int bx0 = blockIdx.x * TL::X, by0 = blockIdx.y * TL::Y, bz0 = blockIdx.z * TL::Z;
+  const long sK = K == 0 ? 1 : (K == 1 ? (long)G.P[0] : (long)G.P[0] * G.P[1]);
   unsigned bad = 0;
-  // eq. ECFlux_curv_2p: sum_m alpha_m sum_{s<m} F(i - s, i - s + m); node i is q[2]
-  ec_pair_acc<D>(G, q[2], q[3], AL1, F, gt, bad);
-  ec_pair_acc<D>(G, q[2], q[4], AL2, F, gt, bad);
-  ec_pair_acc<D>(G, q[1], q[3], AL2, F, gt, bad);
-  ec_pair_acc<D>(G, q[2], q[5], AL3, F, gt, bad);
-  ec_pair_acc<D>(G, q[1], q[4], AL3, F, gt, bad);
-  ec_pair_acc<D>(G, q[0], q[3], AL3, F, gt, bad);
+
+  // ---- phase 1: pair fluxes of the nodes owning pairs of this tile ----
+  for (int q = tid; q < Q; q += 256) {
+    int qx = q % QX, qy = (q / QX) % QY, qz = q / (QX * QY);
+    // node index: along K the first item is the node two below the tile's first left node
+    int i0 = bx0 + qx - (K == 0 ? 3 : 0), i1 = by0 + qy - (K == 1 ? 3 : 0), i2 = bz0 + qz - (K == 2 ? 3 : 0);
+    int ik = K == 0 ? i0 : (K == 1 ? i1 : i2);
+    bool ok = ik <= G.n[K] - 1 && (K == 0 || i0 < G.n[0]) && (K == 1 || i1 < G.n[1]) && (K == 2 || i2 < G.n[2]);
+    if (!ok) continue;
+    long pt = ((long)(i2 + G.g[2]) * G.P[1] + (i1 + G.g[1])) * G.P[0] + (i0 + G.g[0]);
+    Pq<D> a, b;
+    load_pq<D, K>(G, nd, pt, a);
+#pragma unroll
+    for (int m = 1; m <= 3; ++m) {
+      load_pq<D, K>(G, nd, pt + m * sK, b);
+      double o[NC];
+      ec_pair<D>(G, a, b, o, bad);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) sP[(c * 3 + (m - 1)) * Q + q] = o[c];
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 2: this thread's interface ----
+  const int tx = tid % TL::X, ty = (tid / TL::X) % TL::Y, tz = tid / (TL::X * TL::Y);
+  const int a0 = bx0 + tx, a1 = by0 + ty, a2 = bz0 + tz;  // interface index (along K: 0..n_K)
+  const int e0 = G.n[0] + (K == 0), e1 = G.n[1] + (K == 1), e2 = G.n[2] + (K == 2);
+  if (a0 >= e0 || a1 >= e1 || a2 >= e2) {
+    if (bad) raise_flag(flags, ESVDW_F_MEANCONSTRAINT);
+    return;
+  }
+  const int i0 = a0 - (K == 0), i1 = a1 - (K == 1), i2 = a2 - (K == 2);  // left node i
+  // LDS item of node i (local coordinates shifted by 2 along K)
+  const int qi = ((tz + 2 * (K == 2)) * QY + (ty + 2 * (K == 1))) * QX + (tx + 2 * (K == 0));
+  const int qs = K == 0 ? 1 : (K == 1 ? QX : QX * QY);
+  double Fl[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double *P1 = sP + (c * 3 + 0) * Q, *P2 = sP + (c * 3 + 1) * Q, *P3 = sP + (c * 3 + 2) * Q;
+    Fl[c] = AL1 * P1[qi] + AL2 * (P2[qi] + P2[qi - qs]) + AL3 * (P3[qi] + P3[qi - qs] + P3[qi - 2 * qs]);
+  }
 
   if (G.diss) {
-    // averaged state at the interface
-    double rb = logmean(q[2].rho, q[3].rho);
-    double pb = rb / logmean(q[2].rho / q[2].p, q[3].rho / q[3].p);
+    const long pc = ((long)(i2 + G.g[2]) * G.P[1] + (i1 + G.g[1])) * G.P[0] + (i0 + G.g[0]);
+    const long pr = pc + sK;
+    double rl = nd[F::RHO * G.PN + pc], rr = nd[F::RHO * G.PN + pr];
+    double pl = nd[F::P * G.PN + pc], pq = nd[F::P * G.PN + pr];
+    double ilr = inv_logmean(rl, rr, nd[F::LNR * G.PN + pc], nd[F::LNR * G.PN + pr]);
+    // rho/p and its logarithm
+    double zl = rl / pl, zr = rr / pq;
+    double ilz = inv_logmean(zl, zr, nd[F::LNR * G.PN + pc] - nd[F::LNP * G.PN + pc],
+                             nd[F::LNR * G.PN + pr] - nd[F::LNP * G.PN + pr]);
+    double rb = 1.0 / ilr;     // L(rho)
+    double pb = rb * ilz;      // L(rho)/L(rho/p)
     double vb[D];
 #pragma unroll
-    for (int m = 0; m < D; ++m) vb[m] = 0.5 * (q[2].v[m] + q[3].v[m]);
-    double Tb = eos_T_rho_p(G, rb, pb);
+    for (int m = 0; m < D; ++m) vb[m] = 0.5 * (nd[(long)(F::V + m) * G.PN + pc] + nd[(long)(F::V + m) * G.PN + pr]);
     double ob = 1.0 - G.b * rb;
-    double c2 = (1.0 + G.delta) * G.R * Tb / (ob * ob) - 2.0 * G.a * rb;
+    double Tb = (pb + G.a * rb * rb) * ob * ilr * G.iR;
+    double iob = 1.0 / ob;
+    double c2 = (1.0 + G.delta) * G.R * Tb * iob * iob - 2.0 * G.a * rb;
     double mm[D], L2 = 0.0;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      mm[j] = 0.5 * (q[2].m[j] + q[3].m[j]);
+      mm[j] = 0.5 * (nd[(long)(F::MS + K * D + j) * G.PN + pc] + nd[(long)(F::MS + K * D + j) * G.PN + pr]);
       L2 += mm[j] * mm[j];
     }
-    double mtb = 0.5 * (q[2].mt + q[3].mt);
+    double mtb = 0.5 * (nd[(long)(F::XS + K) * G.PN + pc] + nd[(long)(F::XS + K) * G.PN + pr]);
     double L = sqrt(L2);
+    double iL = 1.0 / L;
     Eig<D> E;
 #pragma unroll
-    for (int j = 0; j < D; ++j) E.n[j] = mm[j] / L;
+    for (int j = 0; j < D; ++j) E.n[j] = mm[j] * iL;
     if constexpr (D == 2) {
       E.tg[0][0] = -E.n[1];
       E.tg[0][1] = E.n[0];
@@ -404,8 +463,9 @@ __global__ void k_flux(Geo G, const double *__restrict__ nd, double *__restrict_
       double sxy = sqrt(E.n[0] * E.n[0] + E.n[1] * E.n[1]);
       double ct = 1.0, st = 0.0;
       if (sxy > 0.0) {
-        ct = E.n[0] / sxy;
-        st = E.n[1] / sxy;
+        double is = 1.0 / sxy;
+        ct = E.n[0] * is;
+        st = E.n[1] * is;
       }
       E.tg[0][0] = -st;
       E.tg[0][1] = ct;
@@ -429,22 +489,29 @@ __global__ void k_flux(Geo G, const double *__restrict__ nd, double *__restrict_
       E.ut[t2] = s;
     }
     double Eb = rb * (G.cv * Tb - G.a * rb) + 0.5 * rb * vv;
-    E.H = (Eb + pb) / rb;
+    E.H = (Eb + pb) * ilr;
     E.c = sqrt(c2);
-    E.c2G = c2 * G.cv * ob / G.R;  // c^2 / Gamma with Gamma = R/(c_v (1 - b rho))
+    E.c2G = c2 * G.cv * ob * G.iR;  // c^2 / Gamma with Gamma = R/(c_v (1 - b rho))
     double ac = G.R * Tb - 2.0 * G.a * rb * ob * ob;
-    double S0 = rb * Tb / (2.0 * c2), S1 = G.R * G.R * rb * Tb * Tb / (G.cv * ac * c2), St = rb * Tb;
+    double ic2 = 1.0 / c2;
+    double S0 = 0.5 * rb * Tb * ic2, S1 = G.R * G.R * rb * Tb * Tb * ic2 / (G.cv * ac), St = rb * Tb;
     if (!(S0 > 0.0) || !(S1 > 0.0)) bad = 1u;
     E.s0 = sqrt(fabs(S0));
     E.s1 = sqrt(fabs(S1));
     E.st = sqrt(fabs(St));
     double Lam = fmax(fabs(mtb + L * (un - E.c)), fmax(fabs(mtb + L * un), fabs(mtb + L * (un + E.c))));
     double W[6][NV];
-#pragma unroll
-    for (int s = 0; s < 6; ++s) w_of<D>(E, q[s].V, W[s]);
     double A2[NV], A3[NV];
-    wmag_of<D>(E, q[2].V, A2);
-    wmag_of<D>(E, q[3].V, A3);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      double V[NV];
+      const long ps = pc + (s - 2) * sK;
+#pragma unroll
+      for (int c = 0; c < NV; ++c) V[c] = nd[(long)(F::VS + c) * G.PN + ps];
+      w_of<D>(E, V, W[s]);
+      if (s == 2) wmag_of<D>(E, V, A2);
+      if (s == 3) wmag_of<D>(E, V, A3);
+    }
     double y[NV];
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
@@ -456,10 +523,10 @@ __global__ void k_flux(Geo G, const double *__restrict__ nd, double *__restrict_
       y[c] = ((jr > 0.0 && j0 > 0.0) || (jr < 0.0 && j0 < 0.0)) ? jr : 0.0;
     }
     // R y in the rotated frame, then rotate the momentum back (T^T)
-    double a0 = E.s0 * y[0], a1 = E.s1 * y[1], a2 = E.s0 * y[D + 1];
-    double dr = a0 + a1 + a2;
-    double dn = a0 * (un - E.c) + a1 * un + a2 * (un + E.c);
-    double dE = a0 * (E.H - un * E.c) + a1 * (E.H - E.c2G) + a2 * (E.H + un * E.c);
+    double b0 = E.s0 * y[0], b1 = E.s1 * y[1], b2 = E.s0 * y[D + 1];
+    double dr = b0 + b1 + b2;
+    double dn = b0 * (un - E.c) + b1 * un + b2 * (un + E.c);
+    double dE = b0 * (E.H - un * E.c) + b1 * (E.H - E.c2G) + b2 * (E.H + un * E.c);
     double dt_[D > 1 ? D - 1 : 1];
 #pragma unroll
     for (int t2 = 0; t2 < D - 1; ++t2) {
@@ -467,20 +534,20 @@ __global__ void k_flux(Geo G, const double *__restrict__ nd, double *__restrict_
       dE += E.st * y[2 + t2] * E.ut[t2];
     }
     double h = 0.5 * Lam;
-    F[0] -= h * dr;
+    Fl[0] -= h * dr;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       double mj = E.n[j] * dn;
 #pragma unroll
       for (int t2 = 0; t2 < D - 1; ++t2) mj += E.tg[t2][j] * dt_[t2];
-      F[1 + j] -= h * mj;
+      Fl[1 + j] -= h * mj;
     }
-    F[D + 1] -= h * dE;
+    Fl[D + 1] -= h * dE;
   }
   if (bad) raise_flag(flags, ESVDW_F_MEANCONSTRAINT);
+  const long ti = ((long)a2 * e1 + a1) * e0 + a0;
 #pragma unroll
-  for (int c = 0; c < NV; ++c) Fo[(long)c * nif + t] = F[c];
-  Fo[(long)NV * nif + t] = gt;
+  for (int c = 0; c < NC; ++c) Fo[(long)c * nif + ti] = Fl[c];
 }
 
 // =============================== update ==========================================
@@ -599,6 +666,22 @@ int launch_metrics(esvdw_ctx *c, const double *x, const double *xd, double *met,
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+template <int D, int K> static void launch_flux_dk(esvdw_ctx *c, hipStream_t st) {
+  using TL = Tile<D, K>;
+  const Geo &G = c->G;
+  int e0 = G.n[0] + (K == 0), e1 = G.n[1] + (K == 1), e2 = G.n[2] + (K == 2);
+  dim3 grid((e0 + TL::X - 1) / TL::X, (e1 + TL::Y - 1) / TL::Y, (e2 + TL::Z - 1) / TL::Z);
+  hipLaunchKernelGGL((k_flux<D, K>), grid, dim3(256), 0, st, G, c->node, c->flux[K], c->nif[K], c->flags);
+}
+
+template <int D> static void launch_flux_d(esvdw_ctx *c, int K, hipStream_t st) {
+  if (K == 0) launch_flux_dk<D, 0>(c, st);
+  if constexpr (D > 1)
+    if (K == 1) launch_flux_dk<D, 1>(c, st);
+  if constexpr (D > 2)
+    if (K == 2) launch_flux_dk<D, 2>(c, st);
+}
+
 template <int D>
 static int rhs_pipeline_d(esvdw_ctx *c, const double *JU, const double *J, const double *met, const double *xit,
                           const double *xn, const double *xd, double cdt, int mode, int s, const double *dtp,
@@ -608,15 +691,9 @@ static int rhs_pipeline_d(esvdw_ctx *c, const double *JU, const double *J, const
     if (launch_dprod(c, xn, xd, cdt, st)) return -1;
   hipLaunchKernelGGL(k_nodes<D>, dim3(nblk(G.PN, 256)), dim3(256), 0, st, G, JU, J, met, xit, xn, xd, cdt, c->dprod,
                      c->dpN, c->node, c->flags);
-  constexpr int K1 = D > 1 ? 1 : 0, K2 = D > 2 ? 2 : 0;
-  hipLaunchKernelGGL((k_flux<D, 0>), dim3(nblk(c->nif[0], 128)), dim3(128), 0, st, G, c->node, c->flux[0], c->nif[0],
-                     c->flags);
-  if (D > 1)
-    hipLaunchKernelGGL((k_flux<D, K1>), dim3(nblk(c->nif[1], 128)), dim3(128), 0, st, G, c->node, c->flux[1],
-                       c->nif[1], c->flags);
-  if (D > 2)
-    hipLaunchKernelGGL((k_flux<D, K2>), dim3(nblk(c->nif[2], 128)), dim3(128), 0, st, G, c->node, c->flux[2],
-                       c->nif[2], c->flags);
+  launch_flux_d<D>(c, 0, st);
+  if (D > 1) launch_flux_d<D>(c, 1, st);
+  if (D > 2) launch_flux_d<D>(c, 2, st);
   hipLaunchKernelGGL(k_update<D>, dim3(nblk(G.N, 256)), dim3(256), 0, st, G, c->flux[0], c->flux[1], c->flux[2],
                      c->nif[0], c->nif[1], c->nif[2], mode, s, dtp, bJU, bJ, JU, J, oJU, oJ, c->flags);
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -649,5 +726,13 @@ int launch_axpy_mesh(esvdw_ctx *c, const double *x, const double *xd, const doub
                      hipStream_t st) {
   long n = (long)c->G.dim * c->G.N;
   hipLaunchKernelGGL(k_axpy_mesh, dim3(nblk(n, 256)), dim3(256), 0, st, n, x, xd, dtp, f, out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_flux_only(esvdw_ctx *c, int K, hipStream_t st) {
+  if (K < 0 || K >= c->G.dim) return -1;
+  if (c->G.dim == 1) launch_flux_d<1>(c, K, st);
+  else if (c->G.dim == 2) launch_flux_d<2>(c, K, st);
+  else launch_flux_d<3>(c, K, st);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

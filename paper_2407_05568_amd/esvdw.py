@@ -19,7 +19,7 @@ MONVAR = {"rho": 0, "G": 1}
 # entry points declared in include/esvdw.h
 SYMBOLS = ["esvdw_create", "esvdw_destroy", "esvdw_get_status", "esvdw_strerror", "init_mesh", "init_state",
            "compute_metrics", "es_rhs", "rk_stage", "redistribute_mesh", "mesh_monitor", "mesh_jacobi",
-           "mesh_limiter", "cfl_dt", "esvdw_step"]
+           "mesh_limiter", "cfl_dt", "esvdw_step", "esvdw_bench_kernel"]
 
 
 class Params(ctypes.Structure):
@@ -92,6 +92,7 @@ def lib():
             "mesh_limiter": (I, [_VP] * 5),
             "cfl_dt": (I, [_VP] * 6),
             "esvdw_step": (I, [_VP, _VP, _VP, _VP, I, _VP, _VP]),
+            "esvdw_bench_kernel": (I, [_VP, I, I, _VP]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -191,6 +192,9 @@ class Context:
 
     def cfl_dt(self, JU, J, x, dt_dev, stream=None):
         _check(self.L.cfl_dt(self.h, _ptr(JU), _ptr(J), _ptr(x), _ptr(dt_dev), _stream(stream)), "cfl_dt")
+
+    def bench_kernel(self, which, reps, stream=None):
+        _check(self.L.esvdw_bench_kernel(self.h, int(which), int(reps), _stream(stream)), "esvdw_bench_kernel")
 
     def step(self, JU, J, x, moving, dt_dev, stream=None):
         _check(self.L.esvdw_step(self.h, _ptr(JU), _ptr(J), _ptr(x), int(bool(moving)), _ptr(dt_dev),
