@@ -155,7 +155,9 @@ int esvdw_step(esvdw_ctx *ctx, double *JU, double *J, double *x, int moving, dou
  * context's current scratch contents, so that a caller can bracket it with stream events.
  * which = 1, 2, 3: the interface-flux kernel of direction 1, 2, 3 (reads the node data left
  * by the last RHS evaluation, writes the context's flux buffer); which = 5: one Jacobi sweep
- * of the context's mesh-iteration buffers.  Call only after a step or RHS on this context.
+ * of the context's mesh-iteration buffers; which = 6: a plain copy of 2 (dim + 3) N doubles
+ * between the context's stage buffers (reads and writes 16 (dim + 3) N bytes: a reference for
+ * memory-traffic counters).  Call only after a step or RHS on this context.
  * EINVAL for an unknown kernel or a direction beyond dim. */
 int esvdw_bench_kernel(esvdw_ctx *ctx, int which, int reps, hipStream_t stream);
 

@@ -78,7 +78,7 @@ const char *esvdw_strerror(int code) {
 void esvdw_destroy(esvdw_ctx *c) {
   if (!c) return;
   void *bufs[] = {c->node, c->flux[0], c->flux[1], c->flux[2], c->dprod, c->met, c->stA, c->stB, c->xdot, c->xmu,
-                  c->xtmp, c->omega, c->omega2, c->mterm, c->rhoG, c->scal, c->flags};
+                  c->xtmp, c->omega, c->omega2, c->mterm, c->rhoG, c->scal, c->part, c->flags};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   free(c);
@@ -115,6 +115,12 @@ int esvdw_create(const esvdw_params *p, esvdw_ctx **out) {
   ok = ok && dalloc(&c->xdot, (size_t)D * N) && dalloc(&c->xmu, (size_t)D * N) && dalloc(&c->xtmp, (size_t)D * N);
   ok = ok && dalloc(&c->omega, (size_t)N) && dalloc(&c->omega2, (size_t)N) && dalloc(&c->mterm, (size_t)3 * N);
   ok = ok && dalloc(&c->rhoG, (size_t)2 * N) && dalloc(&c->scal, (size_t)SC_N) && dalloc(&c->flags, 1);
+  {
+    dim3 g, b;
+    node_grid(G.n[0], G.n[1], G.n[2], g, b);
+    c->npart = (long)g.x * g.y * g.z + 1;
+  }
+  ok = ok && dalloc(&c->part, (size_t)4 * c->npart);
   if (ok) ok = HIPOK(hipMemset(c->flags, 0, sizeof(unsigned))) && HIPOK(hipMemset(c->scal, 0, SC_N * sizeof(double)));
   if (ok) ok = HIPOK(hipDeviceSynchronize());
   if (!ok) {
@@ -264,6 +270,12 @@ int esvdw_bench_kernel(esvdw_ctx *c, int which, int reps, hipStream_t st) {
     if (which > c->G.dim) return ESVDW_EINVAL;
     for (int r = 0; r < reps; ++r)
       if (launch_flux_only(c, which - 1, st)) return ESVDW_EHIP;
+    return ESVDW_OK;
+  }
+  if (which == 6) {
+    long n = (long)(c->G.nv + 1) * c->G.N;
+    for (int r = 0; r < reps; ++r)
+      if (launch_copy(c->stA, c->stB, n, st)) return ESVDW_EHIP;
     return ESVDW_OK;
   }
   if (which == 5) {

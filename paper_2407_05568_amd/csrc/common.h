@@ -80,6 +80,67 @@ __device__ __forceinline__ double mesh_at(const Geo &G, const double *__restrict
 }
 
 // ---------------------------------------------------------------------------------
+// discrete metrics (eq. SCLCoeff) on a stage mesh
+// ---------------------------------------------------------------------------------
+// stage-mesh coordinate: x_n + cdt * xdot, both ghost-extended by the mesh maps
+__device__ __forceinline__ double stage_x(const Geo &G, const double *__restrict__ xn, const double *__restrict__ xd,
+                                          double cdt, int j, int i0, int i1, int i2) {
+  double v = mesh_at(G, xn, j, i0, i1, i2, 0);
+  if (xd && cdt != 0.0) v += cdt * mesh_at(G, xd, j, i0, i1, i2, 1);
+  return v;
+}
+
+// delta_k[x_j] at (i0, i1, i2): (1/2) sum_m alpha_m (x_{i+m e_k} - x_{i-m e_k})
+__device__ __forceinline__ double delta_x(const Geo &G, const double *xn, const double *xd, double cdt, int k, int j,
+                                          int i0, int i1, int i2) {
+  int e0 = k == 0, e1 = k == 1, e2 = k == 2;
+  double s = 0.0;
+  const double al[3] = {AL1, AL2, AL3};
+#pragma unroll
+  for (int m = 1; m <= 3; ++m)
+    s += al[m - 1] * (stage_x(G, xn, xd, cdt, j, i0 + m * e0, i1 + m * e1, i2 + m * e2) -
+                      stage_x(G, xn, xd, cdt, j, i0 - m * e0, i1 - m * e1, i2 - m * e2));
+  return 0.5 * s;
+}
+
+__device__ __forceinline__ long dp_index(const Geo &G, int i0, int i1, int i2) {
+  int P0 = G.n[0] + 12, P1 = G.n[1] + 12;
+  return ((long)(i2 + 6) * P1 + (i1 + 6)) * P0 + (i0 + 6);
+}
+
+// metric J dxi_k/dx_j at (i0, i1, i2) from the stage mesh (2D directly, 3D from dprod)
+template <int D>
+__device__ __forceinline__ double metric_at(const Geo &G, const double *xn, const double *xd, double cdt,
+                                            const double *dp, long dpN, int k, int j, int i0, int i1, int i2) {
+  if (D == 1) return 1.0;
+  if (D == 2) {
+    // J dxi_1/dx_1 = x_2,xi2 ; J dxi_1/dx_2 = -x_1,xi2 ; J dxi_2/dx_1 = -x_2,xi1 ; J dxi_2/dx_2 = x_1,xi1
+    int kk = 1 - k, jj = 1 - j;
+    double sg = (k == j) ? 1.0 : -1.0;
+    return sg * delta_x(G, xn, xd, cdt, kk, jj, i0, i1, i2) * G.idxi[kk];
+  }
+  // D == 3: (delta_{k2}[delta_{k1}[x_{j1}] x_{j2}] - delta_{k1}[delta_{k2}[x_{j1}] x_{j2}]) / (dxi_{k1} dxi_{k2})
+  int k1 = (k + 1) % 3, k2 = (k + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+  const double al[3] = {AL1, AL2, AL3};
+  double s = 0.0;
+  for (int term = 0; term < 2; ++term) {
+    int in = term == 0 ? k1 : k2, out = term == 0 ? k2 : k1;
+    int e[3] = {out == 0, out == 1, out == 2};
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 1; m <= 3; ++m) {
+      int a0 = i0 + m * e[0], a1 = i1 + m * e[1], a2 = i2 + m * e[2];
+      int b0 = i0 - m * e[0], b1 = i1 - m * e[1], b2 = i2 - m * e[2];
+      double fa = dp[(long)(in * 3 + j1) * dpN + dp_index(G, a0, a1, a2)] * stage_x(G, xn, xd, cdt, j2, a0, a1, a2);
+      double fb = dp[(long)(in * 3 + j1) * dpN + dp_index(G, b0, b1, b2)] * stage_x(G, xn, xd, cdt, j2, b0, b1, b2);
+      acc += al[m - 1] * (fa - fb);
+    }
+    s += (term == 0 ? 0.5 : -0.5) * acc;
+  }
+  return s * G.idxi[k1] * G.idxi[k2];
+}
+
+// ---------------------------------------------------------------------------------
 // thermodynamics (eq. vdWEOS and the closed forms of Section 2, general units)
 // ---------------------------------------------------------------------------------
 __device__ __forceinline__ double eos_p(const Geo &G, double rho, double T) {
@@ -164,8 +225,9 @@ __device__ __forceinline__ double mrweno5(const Geo &G, double a, double b, doub
 }
 
 // ---------------------------------------------------------------------------------
-// reductions: wavefront (64 lanes) by shuffles, then across the block through LDS,
-// then one device atomic per block on the bit pattern of a non-negative double
+// reductions: wavefront (64 lanes) by shuffles, then across the block through LDS; each
+// block writes one partial, and a one-block kernel reduces the partials (no atomics on a
+// single address)
 // ---------------------------------------------------------------------------------
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
@@ -178,35 +240,58 @@ __device__ __forceinline__ double wave_min(double v) {
   return v;
 }
 
-// block of at most 1024 threads; v >= 0
-__device__ __forceinline__ void block_atomic_max(double v, double *dst) {
+__device__ __forceinline__ int flat_tid() { return threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z); }
+__device__ __forceinline__ int flat_bid() { return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z); }
+__device__ __forceinline__ int block_threads() { return blockDim.x * blockDim.y * blockDim.z; }
+
+// block-wide max / min (any block size up to 1024); the result is valid in thread 0
+__device__ __forceinline__ double block_max(double v) {
   __shared__ double part[16];
   v = wave_max(v);
-  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int ft = flat_tid(), lane = ft & 63, w = ft >> 6;
   if (lane == 0) part[w] = v;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int nw = (blockDim.x + 63) >> 6;
-    double m = part[0];
+  double m = part[0];
+  if (ft == 0) {
+    int nw = (block_threads() + 63) >> 6;
     for (int i = 1; i < nw; ++i) m = fmax(m, part[i]);
-    if (m > 0.0) atomicMax((unsigned long long *)dst, (unsigned long long)__double_as_longlong(m));
   }
+  __syncthreads();
+  return m;
 }
-__device__ __forceinline__ void block_atomic_min(double v, double *dst) {
+__device__ __forceinline__ double block_min(double v) {
   __shared__ double part[16];
   v = wave_min(v);
-  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int ft = flat_tid(), lane = ft & 63, w = ft >> 6;
   if (lane == 0) part[w] = v;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int nw = (blockDim.x + 63) >> 6;
-    double m = part[0];
+  double m = part[0];
+  if (ft == 0) {
+    int nw = (block_threads() + 63) >> 6;
     for (int i = 1; i < nw; ++i) m = fmin(m, part[i]);
-    atomicMin((unsigned long long *)dst, (unsigned long long)__double_as_longlong(m));
   }
+  __syncthreads();
+  return m;
 }
 
 __device__ __forceinline__ void raise_flag(unsigned *flags, unsigned f) { atomicOr(flags, f); }
+
+// Node-wise kernels run on a 3D grid: blockDim (64, 4, 1) (or (256, 1, 1) in 1D), one grid
+// z-slice per z index, so node coordinates need no integer division.
+#define NODE_COORDS(n0, n1)                                                                                  \
+  const int i0 = blockIdx.x * blockDim.x + threadIdx.x, i1 = blockIdx.y * blockDim.y + threadIdx.y,        \
+            i2 = blockIdx.z;                                                                               \
+  const bool inside = i0 < (n0) && i1 < (n1)
+
+static inline void node_grid(int n0, int n1, int n2, dim3 &g, dim3 &b) {
+  if (n1 == 1 && n2 == 1) {
+    b = dim3(256, 1, 1);
+    g = dim3((n0 + 255) / 256, 1, 1);
+  } else {
+    b = dim3(64, 4, 1);
+    g = dim3((n0 + 63) / 64, (n1 + 3) / 4, n2);
+  }
+}
 
 // device scalar slots of a context
 enum { SC_CFL = 0, SC_MON = 1, SC_GAMMA = 4, SC_RESID = 5, SC_DT = 6, SC_N = 8 };
@@ -230,14 +315,15 @@ struct esvdw_ctx {
   double *omega, *omega2, *mterm;  // N, N, 3N
   double *rhoG;      // 2N
   double *scal;      // SC_N doubles
+  double *part;      // per-block partial reductions (4 * max blocks)
+  long npart;        // capacity of part per slot
   unsigned *flags;
 };
 
-// node-buffer field offsets for dimension D: primitives, 1/T, g = R/(1 - b rho) - a rho/T,
-// 1/(1 - b rho), the logarithms of rho, 1 - b rho, T, p, the entropy variables, the metrics
-// J dxi_k/dx_j and J dxi_k/dt
+// node-buffer field offsets for dimension D: primitives, 1/T, 1/(1 - b rho), the logarithms
+// of rho, 1 - b rho, T, p, the first entropy variable V_1 (the others are v/T and -1/T), the
+// metrics J dxi_k/dx_j and J dxi_k/dt
 template <int D> struct NF_ {
-  static constexpr int RHO = 0, V = 1, T = D + 1, P = D + 2, IT = D + 3, GG = D + 4, IOB = D + 5, LNR = D + 6,
-                       LNB = D + 7, LNT = D + 8, LNP = D + 9, VS = D + 10, MS = VS + D + 2, XS = MS + D * D,
-                       COUNT = XS + D;
+  static constexpr int RHO = 0, V = 1, T = D + 1, P = D + 2, IT = D + 3, IOB = D + 4, LNR = D + 5, LNB = D + 6,
+                       LNT = D + 7, LNP = D + 8, V1 = D + 9, MS = D + 10, XS = MS + D * D, COUNT = XS + D;
 };

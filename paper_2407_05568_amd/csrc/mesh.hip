@@ -7,12 +7,6 @@
 
 static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
-__device__ __forceinline__ void coords(const Geo &G, long t, int &i0, int &i1, int &i2) {
-  i0 = (int)(t % G.n[0]);
-  i1 = (int)((t / G.n[0]) % G.n[1]);
-  i2 = (int)(t / ((long)G.n[0] * G.n[1]));
-}
-
 __global__ void k_set_scalars(double *s) {
   if (threadIdx.x == 0) {
     s[SC_CFL] = 0.0;
@@ -40,11 +34,20 @@ __global__ void k_add(const double *__restrict__ a, const double *__restrict__ b
   if (t < n) c[t] = a[t] + b[t];
 }
 
+// reduce nb per-block partials into *dst (mode 0: max, 1: min); one block of 1024 threads
+__global__ void k_final(const double *__restrict__ part, long nb, double *dst, int mode) {
+  double v = mode == 0 ? 0.0 : 1.0;
+  for (long i = threadIdx.x; i < nb; i += blockDim.x) v = mode == 0 ? fmax(v, part[i]) : fmin(v, part[i]);
+  v = mode == 0 ? block_max(v) : block_min(v);
+  if (threadIdx.x == 0) *dst = v;
+}
+
 // ---- monitor -------------------------------------------------------------------
 template <int D>
 __global__ void k_rho_G(Geo G, const double *__restrict__ JU, const double *__restrict__ J, double *__restrict__ rg) {
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (t >= G.N) return;
+  NODE_COORDS(G.n[0], G.n[1]);
+  if (!inside) return;
+  const long t = lin(G, i0, i1, i2);
   double iJ = 1.0 / J[t];
   double rho = JU[t] * iJ, v2 = 0.0;
   for (int m = 0; m < D; ++m) {
@@ -59,13 +62,12 @@ __global__ void k_rho_G(Geo G, const double *__restrict__ JU, const double *__re
 // term t of the monitor at each node; maxima into scal[SC_MON + t]
 template <int D>
 __global__ void k_mon_terms(Geo G, int kind, int kappa, int var0, int var1, const double *__restrict__ rg,
-                            double *__restrict__ term, double *scal) {
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+                            double *__restrict__ term, double *part, long npart) {
+  NODE_COORDS(G.n[0], G.n[1]);
+  const long t = inside ? lin(G, i0, i1, i2) : 0;
   int nterm = kind == ESVDW_MON_VDW ? kappa + 1 : 2;
   double val[3] = {0.0, 0.0, 0.0};
-  if (t < G.N) {
-    int i0, i1, i2;
-    coords(G, t, i0, i1, i2);
+  if (inside) {
     for (int q = 0; q < nterm; ++q) {
       const double *f;
       bool second;
@@ -96,15 +98,16 @@ __global__ void k_mon_terms(Geo G, int kind, int kappa, int var0, int var1, cons
   }
   for (int q = 0; q < 3; ++q) {
     if (q >= nterm) break;
-    block_atomic_max(val[q], scal + SC_MON + q);
-    __syncthreads();
+    double mq = block_max(val[q]);
+    if (flat_tid() == 0) part[q * npart + flat_bid()] = mq;
   }
 }
 
 __global__ void k_mon_omega(Geo G, int nterm, double a0, double a1, double a2, const double *__restrict__ term,
                             const double *__restrict__ scal, double *__restrict__ omega) {
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (t >= G.N) return;
+  NODE_COORDS(G.n[0], G.n[1]);
+  if (!inside) return;
+  const long t = lin(G, i0, i1, i2);
   double al[3] = {a0, a1, a2};
   double s = 1.0;
   for (int q = 0; q < nterm; ++q) {
@@ -117,10 +120,9 @@ __global__ void k_mon_omega(Geo G, int nterm, double a0, double a1, double a2, c
 // omega <- sum_{j in {-1,0,1}^d} 2^-(|j|_1 + d) omega_{i+j}; replicate / wrap at the boundary
 template <int D>
 __global__ void k_filter(Geo G, const double *__restrict__ in, double *__restrict__ out) {
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (t >= G.N) return;
-  int i0, i1, i2;
-  coords(G, t, i0, i1, i2);
+  NODE_COORDS(G.n[0], G.n[1]);
+  if (!inside) return;
+  const long t = lin(G, i0, i1, i2);
   double s = 0.0;
   const int r1 = D > 1, r2 = D > 2;
   for (int j2 = -r2; j2 <= r2; ++j2)
@@ -136,12 +138,11 @@ __global__ void k_filter(Geo G, const double *__restrict__ in, double *__restric
 // ---- Jacobi sweep -----------------------------------------------------------------
 template <int D>
 __global__ void k_jacobi(Geo G, const double *__restrict__ omega, const double *__restrict__ xin,
-                         double *__restrict__ xout, double *resid) {
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+                         double *__restrict__ xout, double *part) {
+  NODE_COORDS(G.n[0], G.n[1]);
+  const long t = inside ? lin(G, i0, i1, i2) : 0;
   double r = 0.0;
-  if (t < G.N) {
-    int i0, i1, i2;
-    coords(G, t, i0, i1, i2);
+  if (inside) {
     double w0 = omega[t];
     double den = 0.0, num[D];
 #pragma unroll
@@ -166,17 +167,19 @@ __global__ void k_jacobi(Geo G, const double *__restrict__ omega, const double *
       xout[(long)j * G.N + t] = v;
     }
   }
-  if (resid) block_atomic_max(r, resid);
+  if (part) {
+    double mr = block_max(r);
+    if (flat_tid() == 0) part[flat_bid()] = mr;
+  }
 }
 
 // ---- limiter ----------------------------------------------------------------------
 template <int D>
-__global__ void k_limiter(Geo G, const double *__restrict__ xn, const double *__restrict__ xmu, double *gam) {
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+__global__ void k_limiter(Geo G, const double *__restrict__ xn, const double *__restrict__ xmu, double *part) {
+  NODE_COORDS(G.n[0], G.n[1]);
+  const long t = inside ? lin(G, i0, i1, i2) : 0;
   double g = 1.0;
-  if (t < G.N) {
-    int i0, i1, i2;
-    coords(G, t, i0, i1, i2);
+  if (inside) {
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       int e0 = k == 0, e1 = k == 1, e2 = k == 2;
@@ -186,16 +189,20 @@ __global__ void k_limiter(Geo G, const double *__restrict__ xn, const double *__
       else if (dx > 0.0) g = fmin(g, (mesh_at(G, xn, k, i0 + e0, i1 + e1, i2 + e2, 0) - x0) / (2.0 * dx));
     }
   }
-  block_atomic_min(g, gam);
+  double mg = block_min(g);
+  if (flat_tid() == 0) part[flat_bid()] = mg;
 }
 
 // ---- CFL ----------------------------------------------------------------------------
+// CFL spectral-radius sum per node; metrics of the mesh x computed in place (1D/2D) or read
+// from met (3D)
 template <int D>
 __global__ void k_cfl(Geo G, const double *__restrict__ JU, const double *__restrict__ J,
-                      const double *__restrict__ met, double *mx) {
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+                      const double *__restrict__ x, const double *__restrict__ met, double *part) {
+  NODE_COORDS(G.n[0], G.n[1]);
+  const long t = inside ? lin(G, i0, i1, i2) : 0;
   double s = 0.0;
-  if (t < G.N) {
+  if (inside) {
     double iJ = 1.0 / J[t];
     double rho = JU[t] * iJ, v[D], v2 = 0.0;
 #pragma unroll
@@ -210,14 +217,17 @@ __global__ void k_cfl(Geo G, const double *__restrict__ JU, const double *__rest
       double L2 = 0.0, vn = 0.0;
 #pragma unroll
       for (int j = 0; j < D; ++j) {
-        double m = met[(long)(k * D + j) * G.N + t];
+        double m;
+        if constexpr (D == 3) m = met[(long)(k * D + j) * G.N + t];
+        else m = metric_at<D>(G, x, nullptr, 0.0, nullptr, 0, k, j, i0, i1, i2);
         L2 += m * m;
         vn += m * v[j];
       }
       s += (fabs(vn) + sqrt(L2) * c) * iJ * G.idxi[k];
     }
   }
-  block_atomic_max(s, mx);
+  double ms = block_max(s);
+  if (flat_tid() == 0) part[flat_bid()] = ms;
 }
 
 __global__ void k_dt(double cfl, double dt_fixed, double *scal, double *dt_out) {
@@ -260,12 +270,15 @@ int launch_add(const double *a, const double *b, double *dst, long n, hipStream_
 template <int D> static int monitor_d(esvdw_ctx *c, const double *JU, const double *J, double *omega, hipStream_t st) {
   const Geo &G = c->G;
   const esvdw_params &p = c->p;
-  dim3 b(256), g(nblk(G.N, 256));
-  hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, st, c->scal);
+  dim3 b, g;
+  node_grid(G.n[0], G.n[1], G.n[2], g, b);
+  const long nb = (long)g.x * g.y * g.z;
   hipLaunchKernelGGL(k_rho_G<D>, g, b, 0, st, G, JU, J, c->rhoG);
   int nterm = p.monitor_kind == ESVDW_MON_VDW ? p.kappa + 1 : 2;
   hipLaunchKernelGGL(k_mon_terms<D>, g, b, 0, st, G, p.monitor_kind, p.kappa, p.mon_var[0], p.mon_var[1], c->rhoG,
-                     c->mterm, c->scal);
+                     c->mterm, c->part, c->npart);
+  for (int q = 0; q < nterm; ++q)
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, c->part + q * c->npart, nb, c->scal + SC_MON + q, 0);
   // filtered result must end in `omega`: start in omega2 when the pass count is odd
   double *cur = (p.n_filter % 2) ? c->omega2 : omega;
   double *oth = (p.n_filter % 2) ? omega : c->omega2;
@@ -290,12 +303,14 @@ int launch_monitor(esvdw_ctx *c, const double *JU, const double *J, double *omeg
 template <int D>
 static int jacobi_d(esvdw_ctx *c, const double *omega, double *x, int nsweep, double *resid_dev, hipStream_t st) {
   const Geo &G = c->G;
-  dim3 b(256), g(nblk(G.N, 256));
+  dim3 b, g;
+  node_grid(G.n[0], G.n[1], G.n[2], g, b);
+  const long nb = (long)g.x * g.y * g.z;
   double *a = x, *o = c->xtmp;
   for (int it = 0; it < nsweep; ++it) {
     bool last = it == nsweep - 1;
-    if (last) hipLaunchKernelGGL(k_set1, dim3(1), dim3(64), 0, st, c->scal + SC_RESID, 0.0);
-    hipLaunchKernelGGL(k_jacobi<D>, g, b, 0, st, G, omega, a, o, last ? c->scal + SC_RESID : nullptr);
+    hipLaunchKernelGGL(k_jacobi<D>, g, b, 0, st, G, omega, a, o, last ? c->part : nullptr);
+    if (last) hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, c->part, nb, c->scal + SC_RESID, 0);
     double *tmp = a;
     a = o;
     o = tmp;
@@ -315,24 +330,28 @@ int launch_jacobi(esvdw_ctx *c, const double *omega, double *x, int nsweep, doub
 
 int launch_limiter(esvdw_ctx *c, const double *xn, const double *xmu, double *gamma_dev, hipStream_t st) {
   const Geo &G = c->G;
-  dim3 b(256), g(nblk(G.N, 256));
-  hipLaunchKernelGGL(k_set1, dim3(1), dim3(64), 0, st, c->scal + SC_GAMMA, 1.0);
-  if (G.dim == 1) hipLaunchKernelGGL(k_limiter<1>, g, b, 0, st, G, xn, xmu, c->scal + SC_GAMMA);
-  else if (G.dim == 2) hipLaunchKernelGGL(k_limiter<2>, g, b, 0, st, G, xn, xmu, c->scal + SC_GAMMA);
-  else hipLaunchKernelGGL(k_limiter<3>, g, b, 0, st, G, xn, xmu, c->scal + SC_GAMMA);
+  dim3 b, g;
+  node_grid(G.n[0], G.n[1], G.n[2], g, b);
+  const long nb = (long)g.x * g.y * g.z;
+  if (G.dim == 1) hipLaunchKernelGGL(k_limiter<1>, g, b, 0, st, G, xn, xmu, c->part);
+  else if (G.dim == 2) hipLaunchKernelGGL(k_limiter<2>, g, b, 0, st, G, xn, xmu, c->part);
+  else hipLaunchKernelGGL(k_limiter<3>, g, b, 0, st, G, xn, xmu, c->part);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, c->part, nb, c->scal + SC_GAMMA, 1);
   if (gamma_dev) launch_copy(c->scal + SC_GAMMA, gamma_dev, 1, st);
   return CHK();
 }
 
 int launch_cfl(esvdw_ctx *c, const double *JU, const double *J, const double *x, double *dt_dev, hipStream_t st) {
   const Geo &G = c->G;
-  dim3 b(256), g(nblk(G.N, 256));
+  dim3 b, g;
+  node_grid(G.n[0], G.n[1], G.n[2], g, b);
+  const long nb = (long)g.x * g.y * g.z;
   if (c->p.dt_fixed <= 0.0) {
-    if (launch_metrics(c, x, nullptr, c->met, nullptr, nullptr, st)) return -1;
-    hipLaunchKernelGGL(k_set1, dim3(1), dim3(64), 0, st, c->scal + SC_CFL, 0.0);
-    if (G.dim == 1) hipLaunchKernelGGL(k_cfl<1>, g, b, 0, st, G, JU, J, c->met, c->scal + SC_CFL);
-    else if (G.dim == 2) hipLaunchKernelGGL(k_cfl<2>, g, b, 0, st, G, JU, J, c->met, c->scal + SC_CFL);
-    else hipLaunchKernelGGL(k_cfl<3>, g, b, 0, st, G, JU, J, c->met, c->scal + SC_CFL);
+    if (G.dim == 3 && launch_metrics(c, x, nullptr, c->met, nullptr, nullptr, st)) return -1;
+    if (G.dim == 1) hipLaunchKernelGGL(k_cfl<1>, g, b, 0, st, G, JU, J, x, c->met, c->part);
+    else if (G.dim == 2) hipLaunchKernelGGL(k_cfl<2>, g, b, 0, st, G, JU, J, x, c->met, c->part);
+    else hipLaunchKernelGGL(k_cfl<3>, g, b, 0, st, G, JU, J, x, c->met, c->part);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, c->part, nb, c->scal + SC_CFL, 0);
   }
   hipLaunchKernelGGL(k_dt, dim3(1), dim3(64), 0, st, c->p.cfl, c->p.dt_fixed, c->scal, dt_dev);
   return CHK();

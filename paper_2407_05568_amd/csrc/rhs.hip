@@ -9,77 +9,23 @@
 
 // =============================== metrics ========================================
 
-// stage-mesh coordinate: x_n + cdt * xdot, both ghost-extended by the mesh maps
-__device__ __forceinline__ double stage_x(const Geo &G, const double *__restrict__ xn, const double *__restrict__ xd,
-                                          double cdt, int j, int i0, int i1, int i2) {
-  double v = mesh_at(G, xn, j, i0, i1, i2, 0);
-  if (xd) v += cdt * mesh_at(G, xd, j, i0, i1, i2, 1);
-  return v;
-}
-
-// delta_k[x_j] at (i0, i1, i2): (1/2) sum_m alpha_m (x_{i+m e_k} - x_{i-m e_k})
-__device__ __forceinline__ double delta_x(const Geo &G, const double *xn, const double *xd, double cdt, int k, int j,
-                                          int i0, int i1, int i2) {
-  int e0 = k == 0, e1 = k == 1, e2 = k == 2;
-  double s = 0.0;
-  const double al[3] = {AL1, AL2, AL3};
-#pragma unroll
-  for (int m = 1; m <= 3; ++m)
-    s += al[m - 1] * (stage_x(G, xn, xd, cdt, j, i0 + m * e0, i1 + m * e1, i2 + m * e2) -
-                      stage_x(G, xn, xd, cdt, j, i0 - m * e0, i1 - m * e1, i2 - m * e2));
-  return 0.5 * s;
-}
-
 // 3D: dprod[q*3 + r] = delta_q[x_r] on a grid padded by 6 in every direction (valid where
 // the q index is within 3 of the interior, which is where it is used)
 __global__ void k_dprod(Geo G, const double *__restrict__ xn, const double *__restrict__ xd, double cdt,
                         double *__restrict__ dp, long dpN) {
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (t >= dpN) return;
-  int P0 = G.n[0] + 12, P1 = G.n[1] + 12;
-  int i0 = (int)(t % P0) - 6, i1 = (int)((t / P0) % P1) - 6, i2 = (int)(t / ((long)P0 * P1)) - 6;
+  const int P0 = G.n[0] + 12, P1 = G.n[1] + 12;
+  NODE_COORDS(P0, P1);
+  if (!inside) return;
+  const long t = ((long)i2 * P1 + i1) * P0 + i0;
+  {
+  const int i0 = (int)(blockIdx.x * blockDim.x + threadIdx.x) - 6,
+            i1 = (int)(blockIdx.y * blockDim.y + threadIdx.y) - 6, i2 = (int)blockIdx.z - 6;
   int ii[3] = {i0, i1, i2};
   for (int q = 0; q < 3; ++q) {
     bool ok = ii[q] >= -3 && ii[q] < G.n[q] + 3;
     for (int r = 0; r < 3; ++r) dp[(long)(q * 3 + r) * dpN + t] = ok ? delta_x(G, xn, xd, cdt, q, r, i0, i1, i2) : 0.0;
   }
-}
-
-__device__ __forceinline__ long dp_index(const Geo &G, int i0, int i1, int i2) {
-  int P0 = G.n[0] + 12, P1 = G.n[1] + 12;
-  return ((long)(i2 + 6) * P1 + (i1 + 6)) * P0 + (i0 + 6);
-}
-
-// metric J dxi_k/dx_j at (i0, i1, i2) from the stage mesh (2D directly, 3D from dprod)
-template <int D>
-__device__ __forceinline__ double metric_at(const Geo &G, const double *xn, const double *xd, double cdt,
-                                            const double *dp, long dpN, int k, int j, int i0, int i1, int i2) {
-  if (D == 1) return 1.0;
-  if (D == 2) {
-    // J dxi_1/dx_1 = x_2,xi2 ; J dxi_1/dx_2 = -x_1,xi2 ; J dxi_2/dx_1 = -x_2,xi1 ; J dxi_2/dx_2 = x_1,xi1
-    int kk = 1 - k, jj = 1 - j;
-    double sg = (k == j) ? 1.0 : -1.0;
-    return sg * delta_x(G, xn, xd, cdt, kk, jj, i0, i1, i2) * G.idxi[kk];
   }
-  // D == 3: (delta_{k2}[delta_{k1}[x_{j1}] x_{j2}] - delta_{k1}[delta_{k2}[x_{j1}] x_{j2}]) / (dxi_{k1} dxi_{k2})
-  int k1 = (k + 1) % 3, k2 = (k + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-  const double al[3] = {AL1, AL2, AL3};
-  double s = 0.0;
-  for (int term = 0; term < 2; ++term) {
-    int in = term == 0 ? k1 : k2, out = term == 0 ? k2 : k1;
-    int e[3] = {out == 0, out == 1, out == 2};
-    double acc = 0.0;
-#pragma unroll
-    for (int m = 1; m <= 3; ++m) {
-      int a0 = i0 + m * e[0], a1 = i1 + m * e[1], a2 = i2 + m * e[2];
-      int b0 = i0 - m * e[0], b1 = i1 - m * e[1], b2 = i2 - m * e[2];
-      double fa = dp[(long)(in * 3 + j1) * dpN + dp_index(G, a0, a1, a2)] * stage_x(G, xn, xd, cdt, j2, a0, a1, a2);
-      double fb = dp[(long)(in * 3 + j1) * dpN + dp_index(G, b0, b1, b2)] * stage_x(G, xn, xd, cdt, j2, b0, b1, b2);
-      acc += al[m - 1] * (fa - fb);
-    }
-    s += (term == 0 ? 0.5 : -0.5) * acc;
-  }
-  return s * G.idxi[k1] * G.idxi[k2];
 }
 
 // interior metrics (compute_metrics) and, optionally, the Jacobian (init_mesh)
@@ -87,9 +33,9 @@ template <int D>
 __global__ void k_metrics(Geo G, const double *__restrict__ xn, const double *__restrict__ xd,
                           const double *__restrict__ dp, long dpN, double *__restrict__ met,
                           double *__restrict__ xit, double *__restrict__ J) {
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (t >= G.N) return;
-  int i0 = (int)(t % G.n[0]), i1 = (int)((t / G.n[0]) % G.n[1]), i2 = (int)(t / ((long)G.n[0] * G.n[1]));
+  NODE_COORDS(G.n[0], G.n[1]);
+  if (!inside) return;
+  const long t = lin(G, i0, i1, i2);
   double m[D][D];
   for (int k = 0; k < D; ++k)
     for (int j = 0; j < D; ++j) m[k][j] = metric_at<D>(G, xn, nullptr, 0.0, dp, dpN, k, j, i0, i1, i2);
@@ -146,10 +92,10 @@ __global__ void k_nodes(Geo G, const double *__restrict__ JU, const double *__re
                         const double *__restrict__ xn, const double *__restrict__ xd, double cdt,
                         const double *__restrict__ dp, long dpN, double *__restrict__ nd, unsigned *flags) {
   using F = NF_<D>;
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (t >= G.PN) return;
-  int p0 = (int)(t % G.P[0]), p1 = (int)((t / G.P[0]) % G.P[1]), p2 = (int)(t / ((long)G.P[0] * G.P[1]));
-  int i0 = p0 - G.g[0], i1 = p1 - G.g[1], i2 = p2 - G.g[2];
+  const int p0 = blockIdx.x * blockDim.x + threadIdx.x, p1 = blockIdx.y * blockDim.y + threadIdx.y, p2 = blockIdx.z;
+  if (p0 >= G.P[0] || p1 >= G.P[1]) return;
+  const long t = ((long)p2 * G.P[1] + p1) * G.P[0] + p0;
+  const int i0 = p0 - G.g[0], i1 = p1 - G.g[1], i2 = p2 - G.g[2];
   long s = state_index(G, i0, i1, i2);
   double iJ = 1.0 / J[s];
   double rho = JU[s] * iJ;
@@ -175,7 +121,6 @@ __global__ void k_nodes(Geo G, const double *__restrict__ JU, const double *__re
   nd[F::T * G.PN + t] = T;
   nd[F::P * G.PN + t] = p;
   nd[F::IT * G.PN + t] = iT;
-  nd[F::GG * G.PN + t] = G.R * iob - G.a * rho * iT;
   nd[F::IOB * G.PN + t] = iob;
   nd[F::LNR * G.PN + t] = lnr;
   nd[F::LNB * G.PN + t] = lnb;
@@ -183,10 +128,7 @@ __global__ void k_nodes(Geo G, const double *__restrict__ JU, const double *__re
   nd[F::LNP * G.PN + t] = lnp;
   // entropy variables: V = (-s + (e + p/rho - |v|^2/2)/T, v/T, -1/T), s = c_v ln T + R ln(1/rho - b)
   double sent = G.cv * lnt + G.R * (lnb - lnr);
-  nd[(long)F::VS * G.PN + t] = -sent + (e + p * irho - 0.5 * v2) * iT;
-#pragma unroll
-  for (int m = 0; m < D; ++m) nd[(long)(F::VS + 1 + m) * G.PN + t] = v[m] * iT;
-  nd[(long)(F::VS + D + 1) * G.PN + t] = -iT;
+  nd[(long)F::V1 * G.PN + t] = -sent + (e + p * irho - 0.5 * v2) * iT;
   // metrics
   if (met_in) {
     unsigned mir;
@@ -259,8 +201,8 @@ __device__ __forceinline__ void load_pq(const Geo &G, const double *__restrict__
   for (int m = 0; m < D; ++m) q.v[m] = nd[(long)(F::V + m) * G.PN + t];
   q.T = nd[F::T * G.PN + t];
   q.iT = nd[F::IT * G.PN + t];
-  q.g = nd[F::GG * G.PN + t];
   q.iob = nd[F::IOB * G.PN + t];
+  q.g = G.R * q.iob - G.a * q.rho * q.iT;  // g = R/(1 - b rho) - a rho/T
   q.lr = nd[F::LNR * G.PN + t];
   q.lb = nd[F::LNB * G.PN + t];
   q.lt = nd[F::LNT * G.PN + t];
@@ -371,7 +313,7 @@ __device__ __forceinline__ void wmag_of(const Eig<D> &E, const double *V, double
 }
 
 template <int D, int K>
-__global__ void __launch_bounds__(256) k_flux(Geo G, const double *__restrict__ nd, double *__restrict__ Fo, long nif,
+__global__ void __launch_bounds__(256, 3) k_flux(Geo G, const double *__restrict__ nd, double *__restrict__ Fo, long nif,
                                               unsigned *flags) {
   using F = NF_<D>;
   using TL = Tile<D, K>;
@@ -506,8 +448,13 @@ __global__ void __launch_bounds__(256) k_flux(Geo G, const double *__restrict__ 
     for (int s = 0; s < 6; ++s) {
       double V[NV];
       const long ps = pc + (s - 2) * sK;
+      {
+        double iT = nd[F::IT * G.PN + ps];
+        V[0] = nd[(long)F::V1 * G.PN + ps];
 #pragma unroll
-      for (int c = 0; c < NV; ++c) V[c] = nd[(long)(F::VS + c) * G.PN + ps];
+        for (int m = 0; m < D; ++m) V[1 + m] = nd[(long)(F::V + m) * G.PN + ps] * iT;
+        V[D + 1] = -iT;
+      }
       w_of<D>(E, V, W[s]);
       if (s == 2) wmag_of<D>(E, V, A2);
       if (s == 3) wmag_of<D>(E, V, A3);
@@ -561,9 +508,9 @@ __global__ void k_update(Geo G, const double *__restrict__ F0, const double *__r
                          const double *__restrict__ in_J, double *__restrict__ out_JU, double *__restrict__ out_J,
                          unsigned *flags) {
   constexpr int NV = D + 2;
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (t >= G.N) return;
-  int i0 = (int)(t % G.n[0]), i1 = (int)((t / G.n[0]) % G.n[1]), i2 = (int)(t / ((long)G.n[0] * G.n[1]));
+  NODE_COORDS(G.n[0], G.n[1]);
+  if (!inside) return;
+  const long t = lin(G, i0, i1, i2);
   double L[NV + 1];
 #pragma unroll
   for (int c = 0; c <= NV; ++c) L[c] = 0.0;
@@ -615,17 +562,19 @@ __global__ void k_update(Geo G, const double *__restrict__ F0, const double *__r
 // =============================== small kernels ===================================
 
 __global__ void k_uniform_mesh(Geo G, double *__restrict__ x) {
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (t >= G.N) return;
-  int ii[3] = {(int)(t % G.n[0]), (int)((t / G.n[0]) % G.n[1]), (int)(t / ((long)G.n[0] * G.n[1]))};
+  NODE_COORDS(G.n[0], G.n[1]);
+  if (!inside) return;
+  const long t = lin(G, i0, i1, i2);
+  int ii[3] = {i0, i1, i2};
   for (int j = 0; j < G.dim; ++j) x[(long)j * G.N + t] = G.lo[j] + (ii[j] + 0.5) * G.dxi[j];
 }
 
 template <int D>
 __global__ void k_init_state(Geo G, const double *__restrict__ prim, const double *__restrict__ J,
                              double *__restrict__ JU) {
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (t >= G.N) return;
+  NODE_COORDS(G.n[0], G.n[1]);
+  if (!inside) return;
+  const long t = lin(G, i0, i1, i2);
   double rho = prim[t], p = prim[(long)(D + 1) * G.N + t];
   double T = eos_T_rho_p(G, rho, p);
   double jj = J[t], v2 = 0.0;
@@ -651,7 +600,9 @@ static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b);
 
 int launch_dprod(esvdw_ctx *c, const double *xn, const double *xd, double cdt, hipStream_t st) {
   if (c->G.dim != 3) return 0;
-  hipLaunchKernelGGL(k_dprod, dim3(nblk(c->dpN, 256)), dim3(256), 0, st, c->G, xn, xd, cdt, c->dprod, c->dpN);
+  dim3 g, b;
+  node_grid(c->G.n[0] + 12, c->G.n[1] + 12, c->G.n[2] + 12, g, b);
+  hipLaunchKernelGGL(k_dprod, g, b, 0, st, c->G, xn, xd, cdt, c->dprod, c->dpN);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -659,7 +610,8 @@ int launch_metrics(esvdw_ctx *c, const double *x, const double *xd, double *met,
                    hipStream_t st) {
   const Geo &G = c->G;
   if (launch_dprod(c, x, nullptr, 0.0, st)) return -1;
-  dim3 b(256), g(nblk(G.N, 256));
+  dim3 b, g;
+  node_grid(G.n[0], G.n[1], G.n[2], g, b);
   if (G.dim == 1) hipLaunchKernelGGL(k_metrics<1>, g, b, 0, st, G, x, xd, c->dprod, c->dpN, met, xit, J);
   else if (G.dim == 2) hipLaunchKernelGGL(k_metrics<2>, g, b, 0, st, G, x, xd, c->dprod, c->dpN, met, xit, J);
   else hipLaunchKernelGGL(k_metrics<3>, g, b, 0, st, G, x, xd, c->dprod, c->dpN, met, xit, J);
@@ -689,12 +641,14 @@ static int rhs_pipeline_d(esvdw_ctx *c, const double *JU, const double *J, const
   const Geo &G = c->G;
   if (!met && D == 3)
     if (launch_dprod(c, xn, xd, cdt, st)) return -1;
-  hipLaunchKernelGGL(k_nodes<D>, dim3(nblk(G.PN, 256)), dim3(256), 0, st, G, JU, J, met, xit, xn, xd, cdt, c->dprod,
-                     c->dpN, c->node, c->flags);
+  dim3 gn, bn, gu, bu;
+  node_grid(G.P[0], G.P[1], G.P[2], gn, bn);
+  node_grid(G.n[0], G.n[1], G.n[2], gu, bu);
+  hipLaunchKernelGGL(k_nodes<D>, gn, bn, 0, st, G, JU, J, met, xit, xn, xd, cdt, c->dprod, c->dpN, c->node, c->flags);
   launch_flux_d<D>(c, 0, st);
   if (D > 1) launch_flux_d<D>(c, 1, st);
   if (D > 2) launch_flux_d<D>(c, 2, st);
-  hipLaunchKernelGGL(k_update<D>, dim3(nblk(G.N, 256)), dim3(256), 0, st, G, c->flux[0], c->flux[1], c->flux[2],
+  hipLaunchKernelGGL(k_update<D>, gu, bu, 0, st, G, c->flux[0], c->flux[1], c->flux[2],
                      c->nif[0], c->nif[1], c->nif[2], mode, s, dtp, bJU, bJ, JU, J, oJU, oJ, c->flags);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -710,12 +664,15 @@ int launch_rhs(esvdw_ctx *c, const double *JU, const double *J, const double *me
 }
 
 int launch_uniform_mesh(esvdw_ctx *c, double *x, hipStream_t st) {
-  hipLaunchKernelGGL(k_uniform_mesh, dim3(nblk(c->G.N, 256)), dim3(256), 0, st, c->G, x);
+  dim3 g, b;
+  node_grid(c->G.n[0], c->G.n[1], c->G.n[2], g, b);
+  hipLaunchKernelGGL(k_uniform_mesh, g, b, 0, st, c->G, x);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_init_state(esvdw_ctx *c, const double *prim, const double *J, double *JU, hipStream_t st) {
-  dim3 b(256), g(nblk(c->G.N, 256));
+  dim3 g, b;
+  node_grid(c->G.n[0], c->G.n[1], c->G.n[2], g, b);
   if (c->G.dim == 1) hipLaunchKernelGGL(k_init_state<1>, g, b, 0, st, c->G, prim, J, JU);
   else if (c->G.dim == 2) hipLaunchKernelGGL(k_init_state<2>, g, b, 0, st, c->G, prim, J, JU);
   else hipLaunchKernelGGL(k_init_state<3>, g, b, 0, st, c->G, prim, J, JU);

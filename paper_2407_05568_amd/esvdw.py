@@ -8,7 +8,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libesvdw.so")
+LIB_PATH = os.environ.get("ESVDW_LIB") or os.path.join(HERE, "libesvdw.so")
 
 OK, EINVAL, EHIP, ENOTIMPL = 0, -1, -2, -3
 F_INADMISSIBLE, F_MEANCONSTRAINT, F_NAN, F_NOTCONVERGED = 1, 2, 4, 8
