@@ -161,6 +161,35 @@ int esvdw_step(esvdw_ctx *ctx, double *JU, double *J, double *x, int moving, dou
  * EINVAL for an unknown kernel or a direction beyond dim. */
 int esvdw_bench_kernel(esvdw_ctx *ctx, int which, int reps, hipStream_t stream);
 
+/* ---- learned warm start for the mesh equations (2D) --------------------------------------
+ * A 50 -> 64 -> 64 -> 2 ReLU MLP proposes the displacement x* - x^n (in units of dxi) of the
+ * converged mesh from node features; the plain Jacobi iteration of redistribute_mesh then
+ * starts from x^n + warm_dx and decides convergence (the network is never trusted alone).
+ * Parameters: MLP_NPARAM = 9360 FP32 values, packed W1[64][64] (inputs 50..63 unused), b1[64],
+ * W2[64][64], b2[64], W3[64][16] (outputs 2..15 unused), b3[16]; W[k][j] maps input k to
+ * output j.  Matrix products run on BF16 operands with FP32 accumulation. */
+#define ESVDW_MLP_NPARAM 9360
+
+/* feat (2 N floats): f1 = |grad_xi rho|^2 / max |grad_xi rho|^2 (second-order central
+ * differences, as in the monitor of Section 4) and f2 = tanh G (eq. fundamental) per node. */
+int mlp_features(esvdw_ctx *ctx, const double *JU, const double *J, float *feat, hipStream_t stream);
+
+/* warm_dx (2 N doubles) = dxi * MLP(5 x 5 stencil of (f1, f2), boundary values replicated),
+ * clipped to +-4 dxi per component. */
+int mlp_infer(esvdw_ctx *ctx, const float *feat, const float *params, double *warm_dx, hipStream_t stream);
+
+/* Training gradient: for the sample list samples[2 s] = frame, samples[2 s + 1] = node index
+ * (s < nsamples) over frames stored frame-major in feats ([frame][2][N] floats, as written by
+ * mlp_features) and targets ([frame][2][N] floats, displacement / dxi), computes
+ * loss = scale * sum_s |MLP(s) - target(s)|^2 into *loss_dev and its gradient with respect to
+ * params into grad (MLP_NPARAM floats, overwritten). */
+int mlp_grad(esvdw_ctx *ctx, const float *feats, const float *targets, const int *samples, long nsamples,
+             float scale, const float *params, float *grad, float *loss_dev, hipStream_t stream);
+
+/* One Adam step (beta1 = 0.9, beta2 = 0.999, eps = 1e-8, bias-corrected at step >= 1) on the FP32
+ * parameters with moment buffers m, v (MLP_NPARAM floats each, zero-initialised by the caller). */
+int mlp_adam(float *params, const float *grad, float *m, float *v, int step, float lr, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -286,4 +286,29 @@ int esvdw_bench_kernel(esvdw_ctx *c, int which, int reps, hipStream_t st) {
   return ESVDW_EINVAL;
 }
 
+int mlp_features(esvdw_ctx *c, const double *JU, const double *J, float *feat, hipStream_t st) {
+  if (!c || !JU || !J || !feat) return ESVDW_EINVAL;
+  if (c->G.dim != 2) return ESVDW_EINVAL;
+  return launch_mlp_feat(c, JU, J, feat, st) ? ESVDW_EHIP : ESVDW_OK;
+}
+
+int mlp_infer(esvdw_ctx *c, const float *feat, const float *params, double *warm_dx, hipStream_t st) {
+  if (!c || !feat || !params || !warm_dx) return ESVDW_EINVAL;
+  if (c->G.dim != 2) return ESVDW_EINVAL;
+  return launch_mlp_infer(c, feat, params, warm_dx, st) ? ESVDW_EHIP : ESVDW_OK;
+}
+
+int mlp_grad(esvdw_ctx *c, const float *feats, const float *targets, const int *samples, long nsamples, float scale,
+             const float *params, float *grad, float *loss_dev, hipStream_t st) {
+  if (!c || !feats || !targets || !samples || !params || !grad || !loss_dev || nsamples < 1) return ESVDW_EINVAL;
+  if (c->G.dim != 2) return ESVDW_EINVAL;
+  return launch_mlp_grad(c, feats, targets, samples, nsamples, scale, params, grad, loss_dev, st) ? ESVDW_EHIP
+                                                                                                 : ESVDW_OK;
+}
+
+int mlp_adam(float *params, const float *grad, float *m, float *v, int step, float lr, hipStream_t st) {
+  if (!params || !grad || !m || !v || step < 1) return ESVDW_EINVAL;
+  return launch_mlp_adam(params, grad, m, v, step, lr, st) ? ESVDW_EHIP : ESVDW_OK;
+}
+
 }  // extern "C"

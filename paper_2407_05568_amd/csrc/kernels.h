@@ -24,3 +24,9 @@ int launch_xdot(esvdw_ctx *c, const double *xn, const double *xmu, const double 
 int launch_copy(const double *src, double *dst, long n, hipStream_t st);
 int launch_add(const double *a, const double *b, double *dst, long n, hipStream_t st);
 int launch_flux_only(esvdw_ctx *c, int K, hipStream_t st);
+int launch_grad_rho_terms(esvdw_ctx *c, const double *JU, const double *J, hipStream_t st);
+int launch_mlp_feat(esvdw_ctx *c, const double *JU, const double *J, float *feat, hipStream_t st);
+int launch_mlp_infer(esvdw_ctx *c, const float *feat, const float *P, double *warm, hipStream_t st);
+int launch_mlp_grad(esvdw_ctx *c, const float *feats, const float *tgt, const int *samples, long nsamp, float scale,
+                    const float *P, float *grad, float *loss, hipStream_t st);
+int launch_mlp_adam(float *P, const float *grad, float *m, float *v, int step, float lr, hipStream_t st);

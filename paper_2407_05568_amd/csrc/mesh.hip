@@ -363,3 +363,25 @@ int launch_xdot(esvdw_ctx *c, const double *xn, const double *xmu, const double 
   hipLaunchKernelGGL(k_xdot, dim3(nblk(n, 256)), dim3(256), 0, st, n, xn, xmu, gam, dtp, xdot);
   return CHK();
 }
+
+// ---- |grad_xi rho|^2 per node and its global max (features of the learned warm start) -------
+template <int D> static int grad_rho_d(esvdw_ctx *c, const double *JU, const double *J, hipStream_t st) {
+  const Geo &G = c->G;
+  dim3 b, g;
+  node_grid(G.n[0], G.n[1], G.n[2], g, b);
+  const long nb = (long)g.x * g.y * g.z;
+  hipLaunchKernelGGL(k_rho_G<D>, g, b, 0, st, G, JU, J, c->rhoG);
+  // vdW form with one gradient term of rho: term 0 = |grad rho|^2 (term 1 = |Delta G|^2, unused)
+  hipLaunchKernelGGL(k_mon_terms<D>, g, b, 0, st, G, (int)ESVDW_MON_VDW, 1, (int)ESVDW_VAR_RHO, 0, c->rhoG, c->mterm,
+                     c->part, c->npart);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, c->part, nb, c->scal + SC_MON, 0);
+  return CHK();
+}
+
+int launch_grad_rho_terms(esvdw_ctx *c, const double *JU, const double *J, hipStream_t st) {
+  switch (c->G.dim) {
+    case 1: return grad_rho_d<1>(c, JU, J, st);
+    case 2: return grad_rho_d<2>(c, JU, J, st);
+    default: return grad_rho_d<3>(c, JU, J, st);
+  }
+}

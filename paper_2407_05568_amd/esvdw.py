@@ -19,7 +19,9 @@ MONVAR = {"rho": 0, "G": 1}
 # entry points declared in include/esvdw.h
 SYMBOLS = ["esvdw_create", "esvdw_destroy", "esvdw_get_status", "esvdw_strerror", "init_mesh", "init_state",
            "compute_metrics", "es_rhs", "rk_stage", "redistribute_mesh", "mesh_monitor", "mesh_jacobi",
-           "mesh_limiter", "cfl_dt", "esvdw_step", "esvdw_bench_kernel"]
+           "mesh_limiter", "cfl_dt", "esvdw_step", "esvdw_bench_kernel", "mlp_features", "mlp_infer",
+           "mlp_grad", "mlp_adam"]
+MLP_NPARAM = 9360
 
 
 class Params(ctypes.Structure):
@@ -93,6 +95,10 @@ def lib():
             "cfl_dt": (I, [_VP] * 6),
             "esvdw_step": (I, [_VP, _VP, _VP, _VP, I, _VP, _VP]),
             "esvdw_bench_kernel": (I, [_VP, I, I, _VP]),
+            "mlp_features": (I, [_VP] * 5),
+            "mlp_infer": (I, [_VP] * 5),
+            "mlp_grad": (I, [_VP, _VP, _VP, _VP, ctypes.c_long, ctypes.c_float, _VP, _VP, _VP, _VP]),
+            "mlp_adam": (I, [_VP, _VP, _VP, _VP, I, ctypes.c_float, _VP]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -196,6 +202,21 @@ class Context:
     def bench_kernel(self, which, reps, stream=None):
         _check(self.L.esvdw_bench_kernel(self.h, int(which), int(reps), _stream(stream)), "esvdw_bench_kernel")
 
+    def mlp_features(self, JU, J, feat, stream=None):
+        _check(self.L.mlp_features(self.h, _ptr(JU), _ptr(J), _ptr(feat), _stream(stream)), "mlp_features")
+
+    def mlp_infer(self, feat, params, warm_dx, stream=None):
+        _check(self.L.mlp_infer(self.h, _ptr(feat), _ptr(params), _ptr(warm_dx), _stream(stream)), "mlp_infer")
+
+    def mlp_grad(self, feats, targets, samples, nsamples, scale, params, grad, loss_dev, stream=None):
+        _check(self.L.mlp_grad(self.h, _ptr(feats), _ptr(targets), _ptr(samples), int(nsamples), float(scale),
+                               _ptr(params), _ptr(grad), _ptr(loss_dev), _stream(stream)), "mlp_grad")
+
     def step(self, JU, J, x, moving, dt_dev, stream=None):
         _check(self.L.esvdw_step(self.h, _ptr(JU), _ptr(J), _ptr(x), int(bool(moving)), _ptr(dt_dev),
                                  _stream(stream)), "esvdw_step")
+
+
+def mlp_adam(params, grad, m, v, step, lr, stream=None):
+    _check(lib().mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr), _stream(stream)),
+           "mlp_adam")
