@@ -1,0 +1,172 @@
+"""GPU parity of the learned warm start kernels (BF16 operands, FP32 accumulation on the
+matrix cores) against the FP64 reference in oracle/mlp_oracle.py.
+
+Tolerances come from the arithmetic: features are FP32 roundings of FP64 values (relative
+error <= 2^-24 plus the FP32 tanh); the network rounds operands to BF16 exactly as the
+reference does, so the two differ by FP32 accumulation order (~1e-6 relative) and by the rare
+BF16 rounding decision that a 1e-6 difference moves across a rounding boundary: one such flip
+changes a hidden value by one BF16 unit (2^-8 relative) and an output by about
+2^-8 |h| |w| <= 5e-3 of the output scale.  So per element max |gpu - ref| <= 5e-3 max |ref|,
+and over all elements ||gpu - ref|| <= 1e-3 ||ref||."""
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as mo
+from paper_2407_05568_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2407_05568_amd import esvdw
+    esvdw.lib()
+    return torch
+
+
+def _f32(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _f64(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _close(g, r, elem=5e-3, norm=1e-3):
+    g, r = np.asarray(g, np.float64).ravel(), np.asarray(r, np.float64).ravel()
+    scale = np.abs(r).max()
+    assert np.abs(g - r).max() <= elem * scale, (np.abs(g - r).max(), scale)
+    assert np.linalg.norm(g - r) <= norm * np.linalg.norm(r), (np.linalg.norm(g - r), np.linalg.norm(r))
+
+
+def _G_field(o, U):
+    ny, nx = U.shape[1:]
+    G = np.zeros((ny, nx))
+    for j in range(ny):
+        for i in range(nx):
+            pr = o.cons_to_prim(U[:, j, i])
+            G[j, i] = o.eos_state(pr[0], pr[-1])["G"]
+    return G
+
+
+@pytest.mark.parametrize("bc,shape,seed", [("outflow", (37, 29), 3), ("periodic", (32, 24), 4)])
+def test_features(torch_dev, orc, bc, shape, seed):
+    torch = torch_dev
+    from paper_2407_05568_amd.esvdw import Context
+    nx, ny = shape
+    p = synth.problem(2, [nx, ny], bc=bc)
+    o = orc.Oracle(p)
+    x = synth.smooth_mesh(p, seed, amp=0.02)
+    J = o.jacobian(x)
+    JU = o.init_state(synth.smooth_state(p, seed + 1, x=x), J)
+    ctx = Context(p)
+    feat = torch.zeros((2, ny, nx), dtype=torch.float32, device="cuda")
+    ctx.mlp_features(_f64(torch, JU), _f64(torch, J), feat)
+    got = feat.cpu().numpy()
+    f1, f2 = mo.features_from_fields(JU[0] / J, _G_field(o, JU / J), [1.0 / nx, 1.0 / ny], (bc, bc))
+    assert np.abs(got[0] - f1).max() <= 1e-6
+    assert np.abs(got[1] - f2).max() <= 1e-6
+
+
+def _random_features(rng, ny, nx):
+    f1 = rng.random((ny, nx)) ** 3
+    f1 /= f1.max()
+    f2 = np.tanh(rng.normal(scale=1.5, size=(ny, nx)))
+    return np.stack([f1, f2]).astype(np.float32)
+
+
+@pytest.mark.parametrize("shape,bc", [((37, 29), "outflow"), ((16, 16), "periodic"), ((7, 9), "outflow")])
+def test_infer(torch_dev, shape, bc):
+    torch = torch_dev
+    from paper_2407_05568_amd.esvdw import Context
+    nx, ny = shape
+    p = synth.problem(2, [max(nx, 6), max(ny, 6)], bc=bc)
+    nx, ny = p["n"][0], p["n"][1]
+    rng = np.random.default_rng(nx * 131 + ny)
+    feat = _random_features(rng, ny, nx)
+    P = mo.init_params(nx + ny).astype(np.float32)
+    P[mo.SLICES["b1"][0]:mo.SLICES["b1"][1]] = rng.normal(scale=0.1, size=64)
+    ctx = Context(p)
+    warm = torch.zeros((2, ny, nx), dtype=torch.float64, device="cuda")
+    ctx.mlp_infer(_f32(torch, feat), _f32(torch, P), warm)
+    X = np.array([mo.stencil(feat[0].astype(np.float64), feat[1].astype(np.float64), i, j, (bc, bc))
+                  for j in range(ny) for i in range(nx)])
+    y, _ = mo.forward(P.astype(np.float64), X)
+    dxi = np.array([1.0 / nx, 1.0 / ny])  # cell-centred nodes on [0, 1]^2
+    ref = np.clip(y * dxi, -4 * dxi, 4 * dxi).T.reshape(2, ny, nx)
+    _close(warm.cpu().numpy(), ref)
+
+
+def test_infer_full_size_sampled(torch_dev):
+    """1024 x 1024 nodes (grid-stride loop over 65536 row groups): sampled nodes against the reference."""
+    torch = torch_dev
+    from paper_2407_05568_amd.esvdw import Context
+    n = 1024
+    p = synth.problem(2, [n, n], bc="outflow")
+    rng = np.random.default_rng(7)
+    feat = _random_features(rng, n, n)
+    P = mo.init_params(11).astype(np.float32)
+    ctx = Context(p)
+    warm = torch.zeros((2, n, n), dtype=torch.float64, device="cuda")
+    ctx.mlp_infer(_f32(torch, feat), _f32(torch, P), warm)
+    w = warm.cpu().numpy()
+    idx = np.concatenate([rng.integers(0, n * n, 2000), [0, n - 1, n * n - 1, n * n - n]])
+    X = np.array([mo.stencil(feat[0].astype(np.float64), feat[1].astype(np.float64), k % n, k // n,
+                             ("outflow", "outflow")) for k in idx])
+    y, _ = mo.forward(P.astype(np.float64), X)
+    dxi = 1.0 / n
+    ref = np.clip(y * dxi, -4 * dxi, 4 * dxi)
+    got = np.stack([w[0].ravel()[idx], w[1].ravel()[idx]], 1)
+    _close(got, ref)
+    assert np.all(np.isfinite(w))
+
+
+@pytest.mark.parametrize("nsamp,nframes", [(100, 1), (1000, 3), (16, 2)])
+def test_grad(torch_dev, nsamp, nframes):
+    torch = torch_dev
+    from paper_2407_05568_amd.esvdw import Context
+    nx, ny = 33, 27
+    p = synth.problem(2, [nx, ny], bc="outflow")
+    rng = np.random.default_rng(nsamp + nframes)
+    feats = np.stack([_random_features(rng, ny, nx) for _ in range(nframes)])
+    tgt = (rng.normal(size=(nframes, 2, ny, nx)) * 0.5).astype(np.float32)
+    frames = rng.integers(0, nframes, nsamp)
+    nodes = rng.integers(0, nx * ny, nsamp)
+    samples = np.stack([frames, nodes], 1).astype(np.int32)
+    P = mo.init_params(5).astype(np.float32)
+    P[mo.SLICES["b2"][0]:mo.SLICES["b2"][1]] = rng.normal(scale=0.1, size=64)
+    ctx = Context(p)
+    grad = torch.zeros(mo.NPARAM, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    scale = 1.0 / nsamp
+    ctx.mlp_grad(_f32(torch, feats), _f32(torch, tgt), torch.from_numpy(samples).cuda(), nsamp, scale,
+                 _f32(torch, P), grad, loss)
+    X = np.array([mo.stencil(feats[f, 0].astype(np.float64), feats[f, 1].astype(np.float64), k % nx, k // nx,
+                             ("outflow", "outflow")) for f, k in samples])
+    Tt = np.array([tgt[f, :, k // nx, k % nx] for f, k in samples], dtype=np.float64)
+    lref, gref = mo.loss_and_grad(P.astype(np.float64), X, Tt, scale)
+    assert abs(loss.item() - lref) <= 1e-4 * abs(lref)
+    g = grad.cpu().numpy()
+    _close(g, gref, elem=1e-2, norm=2e-3)
+    # padded entries receive no gradient
+    a, b, _ = mo.SLICES["W1"]
+    assert np.all(g[a + mo.N_IN * 64:b] == 0)
+
+
+def test_adam(torch_dev):
+    torch = torch_dev
+    from paper_2407_05568_amd import esvdw
+    rng = np.random.default_rng(2)
+    P = rng.normal(size=mo.NPARAM).astype(np.float32)
+    m = np.zeros(mo.NPARAM, np.float32)
+    v = np.zeros(mo.NPARAM, np.float32)
+    Pd, md, vd = _f32(torch, P), _f32(torch, m), _f32(torch, v)
+    Pr, mr, vr = P.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    for step in range(1, 4):
+        g = rng.normal(size=mo.NPARAM).astype(np.float32)
+        esvdw.mlp_adam(Pd, _f32(torch, g), md, vd, step, 1e-3)
+        Pr, mr, vr = mo.adam(Pr, g.astype(np.float64), mr, vr, step, 1e-3)
+    torch.cuda.synchronize()
+    assert np.abs(Pd.cpu().numpy() - Pr).max() <= 1e-5
