@@ -32,8 +32,37 @@ FLOPS_PER_NODE_STAGE_2D = 2 * FLOPS_PER_IFACE_2D + 120
 # (rho, v1, v2, T, p, 1/T, g, 4 entropy variables, 4 metrics, 2 grid-speed metrics) and one
 # write of the 5 flux values
 BYTES_PER_IFACE_2D = 17 * 8 + 5 * 8
+# the copy kernel of esvdw_bench_kernel(6): 2 (dim + 3) N doubles, read once and written once
+COPY_DOUBLES_2D = lambda n: 5 * n * n
 PEAK_FP64 = 78.6e12  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 FLOP/clk
 PEAK_HBM = 8.0e12
+
+
+def kernel_source_hash():
+    """Hash of the sources the flux kernel is built from (the counters are void once they change)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("rhs.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_2407_05568_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(n):
+    """HBM bytes per k_flux launch from the committed counter summary (FETCH_SIZE + WRITE_SIZE,
+    each scaled by the copy kernel's reading), if it was taken on the current kernel source
+    at this size; else None."""
+    path = os.path.join(ROOT, "profiles", "k_flux_2d_1024_counters.md")
+    try:
+        with open(path) as f:
+            txt = f.read()
+        blob = txt.split("```json")[1].split("```")[0]
+        d = json.loads(blob)
+    except (OSError, IndexError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_source_hash() or d.get("size") != n:
+        return None
+    return d.get("traffic_bytes_per_launch")
 
 
 def cpu_baseline(size, seed):
@@ -133,10 +162,14 @@ def main():
     k1.record(stream)
     torch.cuda.synchronize()
     t_launch = k0.elapsed_time(k1) / 1e3 / (2 * reps)
+    # plain copy of a known size (reads and writes COPY_BYTES each): the calibration kernel of
+    # the hardware byte counters
+    ctx.bench_kernel(6, 2, stream)
+    torch.cuda.synchronize()
     nif = (n + 1) * n
     achieved = FLOPS_PER_IFACE_2D * nif / t_launch
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64, "traffic": None,
+                "frac": achieved / PEAK_FP64, "traffic": measured_traffic(n),
                 "kernel": "k_flux (2D interface flux, %d interfaces per launch)" % nif,
                 "avg_launch_ms": t_launch * 1e3,
                 "algorithmic_bytes_GBps": BYTES_PER_IFACE_2D * nif / t_launch / 1e9}

@@ -142,6 +142,10 @@ int mesh_monitor(esvdw_ctx *ctx, const double *JU, const double *J, double *omeg
 int mesh_jacobi(esvdw_ctx *ctx, const double *omega, double *x, int nsweep, double *resid_dev,
                 hipStream_t stream);
 int mesh_limiter(esvdw_ctx *ctx, const double *x_n, const double *x_mu, double *gamma_dev, hipStream_t stream);
+/* mesh_converged: copies into xmu_out (dim fields) the Jacobi result x^[mu] of the last
+ *   redistribute_mesh call on this context, before the movement limiter (Section 4); the
+ *   target of the learned warm start.  Stream-ordered after that call. */
+int mesh_converged(esvdw_ctx *ctx, double *xmu_out, hipStream_t stream);
 int cfl_dt(esvdw_ctx *ctx, const double *JU, const double *J, const double *x, double *dt_dev,
            hipStream_t stream);
 
@@ -175,7 +179,8 @@ int esvdw_bench_kernel(esvdw_ctx *ctx, int which, int reps, hipStream_t stream);
 int mlp_features(esvdw_ctx *ctx, const double *JU, const double *J, float *feat, hipStream_t stream);
 
 /* warm_dx (2 N doubles) = dxi * MLP(5 x 5 stencil of (f1, f2), boundary values replicated),
- * clipped to +-4 dxi per component. */
+ * clipped to +-64 dxi per component (a guard only: the Jacobi iteration that follows is
+ * linear in x and converges from any start). */
 int mlp_infer(esvdw_ctx *ctx, const float *feat, const float *params, double *warm_dx, hipStream_t stream);
 
 /* Training gradient: for the sample list samples[2 s] = frame, samples[2 s + 1] = node index

@@ -245,6 +245,11 @@ int redistribute_mesh(esvdw_ctx *c, const double *JU, const double *J, const dou
   return ESVDW_OK;
 }
 
+int mesh_converged(esvdw_ctx *c, double *xmu_out, hipStream_t st) {
+  if (!c || !xmu_out) return ESVDW_EINVAL;
+  return launch_copy(c->xmu, xmu_out, (long)c->G.dim * c->G.N, st) ? ESVDW_EHIP : ESVDW_OK;
+}
+
 int esvdw_step(esvdw_ctx *c, double *JU, double *J, double *x, int moving, double *dt_dev, hipStream_t st) {
   if (!c || !JU || !J || !x || !dt_dev) return ESVDW_EINVAL;
   long N = c->G.N;

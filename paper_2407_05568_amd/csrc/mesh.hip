@@ -4,6 +4,7 @@
 // device scalar of the context.
 #include "common.h"
 #include "kernels.h"
+#include "scheme.h"
 
 static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -194,38 +195,12 @@ __global__ void k_limiter(Geo G, const double *__restrict__ xn, const double *__
 }
 
 // ---- CFL ----------------------------------------------------------------------------
-// CFL spectral-radius sum per node; metrics of the mesh x computed in place (1D/2D) or read
-// from met (3D)
+// CFL spectral-radius sum per node (cfl_rate); per-block maxima into part
 template <int D>
 __global__ void k_cfl(Geo G, const double *__restrict__ JU, const double *__restrict__ J,
                       const double *__restrict__ x, const double *__restrict__ met, double *part) {
   NODE_COORDS(G.n[0], G.n[1]);
-  const long t = inside ? lin(G, i0, i1, i2) : 0;
-  double s = 0.0;
-  if (inside) {
-    double iJ = 1.0 / J[t];
-    double rho = JU[t] * iJ, v[D], v2 = 0.0;
-#pragma unroll
-    for (int m = 0; m < D; ++m) {
-      v[m] = JU[(long)(1 + m) * G.N + t] * iJ / rho;
-      v2 += v[m] * v[m];
-    }
-    double T = eos_T_rho_e(G, rho, JU[(long)(D + 1) * G.N + t] * iJ / rho - 0.5 * v2);
-    double c = sqrt(eos_c2(G, rho, T));
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      double L2 = 0.0, vn = 0.0;
-#pragma unroll
-      for (int j = 0; j < D; ++j) {
-        double m;
-        if constexpr (D == 3) m = met[(long)(k * D + j) * G.N + t];
-        else m = metric_at<D>(G, x, nullptr, 0.0, nullptr, 0, k, j, i0, i1, i2);
-        L2 += m * m;
-        vn += m * v[j];
-      }
-      s += (fabs(vn) + sqrt(L2) * c) * iJ * G.idxi[k];
-    }
-  }
+  double s = inside ? cfl_rate<D>(G, JU, J, x, met, i0, i1, i2) : 0.0;
   double ms = block_max(s);
   if (flat_tid() == 0) part[flat_bid()] = ms;
 }

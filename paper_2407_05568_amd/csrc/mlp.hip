@@ -119,7 +119,7 @@ __global__ void k_mlp_feat(Geo G, const double *__restrict__ rg, const double *_
   feat[G.N + t] = (float)tanh(rg[G.N + t]);
 }
 
-// ---- inference: warm_dx = dxi * y, clipped to +-4 dxi -------------------------------------
+// ---- inference: warm_dx = dxi * y, clipped to +-64 dxi ------------------------------------
 __global__ void __launch_bounds__(256) k_mlp_infer(Geo G, const float *__restrict__ feat, const float *__restrict__ P,
                                                    double *__restrict__ warm) {
   __shared__ MlpLds s;
@@ -148,7 +148,7 @@ __global__ void __launch_bounds__(256) k_mlp_infer(Geo G, const float *__restric
         long node = g * 16 + rb + r;
         if (node < G.N) {
           double d = G.dxi[col] * (double)y[r];
-          d = fmin(fmax(d, -4.0 * G.dxi[col]), 4.0 * G.dxi[col]);
+          d = fmin(fmax(d, -64.0 * G.dxi[col]), 64.0 * G.dxi[col]);
           warm[(long)col * G.N + node] = d;
         }
       }

@@ -1,0 +1,551 @@
+// scheme.h -- device-level building blocks of the entropy-stable moving-mesh scheme
+// (Sections 3.1-3.3 and the CFL condition of Section 5), shared by the single-problem
+// kernels and the batched persistent stage kernel:
+//   node_point    per padded node: primitives, 1/T, logarithms, entropy variable, metrics
+//   flux_tile     one 256-thread tile of interfaces: sixth-order EC flux + MR-WENO dissipation
+//   update_point  flux differences and the SSP-RK3 stage combination at one node
+//   cfl_rate      sum over directions of the spectral radius over J dxi at one node
+#pragma once
+#include "common.h"
+
+// =============================== node data =======================================
+
+// Metrics given at interior nodes only (es_rhs): ghost values by the boundary symmetry.
+// Outflow mirror normal to q flips J dxi_k/dx_j iff exactly one of k, j is q, and J dxi_k/dt iff k = q.
+__device__ __forceinline__ long ghost_metric_src(const Geo &G, int i0, int i1, int i2, unsigned &mirror) {
+  int ii[3] = {i0, i1, i2};
+  mirror = 0;
+  for (int q = 0; q < G.dim; ++q) {
+    int i = ii[q], n = G.n[q];
+    if (i >= 0 && i < n) continue;
+    if (G.bc[q] == ESVDW_BC_PERIODIC) {
+      ii[q] = i - floordiv(i, n) * n;
+    } else {
+      ii[q] = i < 0 ? -1 - i : 2 * n - 1 - i;
+      mirror |= 1u << q;
+    }
+  }
+  return lin(G, ii[0], ii[1], ii[2]);
+}
+
+// node data of padded node (p0, p1, p2) into the node buffer nd
+template <int D>
+__device__ __forceinline__ void node_point(const Geo &G, const double *__restrict__ JU, const double *__restrict__ J,
+                                           const double *__restrict__ met_in, const double *__restrict__ xit_in,
+                                           const double *__restrict__ xn, const double *__restrict__ xd, double cdt,
+                                           const double *__restrict__ dp, long dpN, double *__restrict__ nd,
+                                           unsigned *flags, int p0, int p1, int p2) {
+  using F = NF_<D>;
+  const long t = ((long)p2 * G.P[1] + p1) * G.P[0] + p0;
+  const int i0 = p0 - G.g[0], i1 = p1 - G.g[1], i2 = p2 - G.g[2];
+  long s = state_index(G, i0, i1, i2);
+  double iJ = 1.0 / J[s];
+  double rho = JU[s] * iJ;
+  double irho = 1.0 / rho;
+  double v[D], v2 = 0.0;
+#pragma unroll
+  for (int m = 0; m < D; ++m) {
+    v[m] = JU[(long)(1 + m) * G.N + s] * iJ * irho;
+    v2 += v[m] * v[m];
+  }
+  double e = JU[(long)(D + 1) * G.N + s] * iJ * irho - 0.5 * v2;
+  double T = (e + G.a * rho) / G.cv;
+  double iT = 1.0 / T;
+  double ob = 1.0 - G.b * rho;
+  double iob = 1.0 / ob;
+  double p = rho * G.R * T * iob - G.a * rho * rho;
+  bool interior = (i0 >= 0 && i0 < G.n[0]) && (i1 >= 0 && i1 < G.n[1]) && (i2 >= 0 && i2 < G.n[2]);
+  if (interior && !admissible(G, rho, T)) raise_flag(flags, ESVDW_F_INADMISSIBLE);
+  double lnr = log(rho), lnb = log(ob), lnt = log(T), lnp = log(p);
+  nd[F::RHO * G.PN + t] = rho;
+#pragma unroll
+  for (int m = 0; m < D; ++m) nd[(long)(F::V + m) * G.PN + t] = v[m];
+  nd[F::T * G.PN + t] = T;
+  nd[F::P * G.PN + t] = p;
+  nd[F::IT * G.PN + t] = iT;
+  nd[F::IOB * G.PN + t] = iob;
+  nd[F::LNR * G.PN + t] = lnr;
+  nd[F::LNB * G.PN + t] = lnb;
+  nd[F::LNT * G.PN + t] = lnt;
+  nd[F::LNP * G.PN + t] = lnp;
+  // entropy variables: V = (-s + (e + p/rho - |v|^2/2)/T, v/T, -1/T), s = c_v ln T + R ln(1/rho - b)
+  double sent = G.cv * lnt + G.R * (lnb - lnr);
+  nd[(long)F::V1 * G.PN + t] = -sent + (e + p * irho - 0.5 * v2) * iT;
+  // metrics
+  if (met_in) {
+    unsigned mir;
+    long ms = ghost_metric_src(G, i0, i1, i2, mir);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        double sg = 1.0;
+        for (int q = 0; q < D; ++q)
+          if ((mir >> q) & 1u)
+            if ((k == q) != (j == q)) sg = -sg;
+        nd[(long)(F::MS + k * D + j) * G.PN + t] = sg * met_in[(long)(k * D + j) * G.N + ms];
+      }
+      double xv = 0.0;
+      if (xit_in) {
+        double sg = ((mir >> k) & 1u) ? -1.0 : 1.0;
+        xv = sg * xit_in[(long)k * G.N + ms];
+      }
+      nd[(long)(F::XS + k) * G.PN + t] = xv;
+    }
+  } else {
+    double m[D][D];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        m[k][j] = metric_at<D>(G, xn, xd, cdt, dp, dpN, k, j, i0, i1, i2);
+        nd[(long)(F::MS + k * D + j) * G.PN + t] = m[k][j];
+      }
+    double xv[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) xv[j] = xd ? mesh_at(G, xd, j, i0, i1, i2, 1) : 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      double s2 = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) s2 -= xv[j] * m[k][j];
+      nd[(long)(F::XS + k) * G.PN + t] = s2;
+    }
+  }
+}
+
+
+// =============================== interface fluxes ================================
+//
+// One block owns a tile of interfaces normal to direction K.  Phase 1: every node that
+// owns a pair flux used by the tile (the tile's nodes along K plus two more on the low
+// side) computes its three two-point fluxes F(i, i+m), m = 1, 2, 3, into LDS.  Phase 2:
+// each thread combines the six pair fluxes of its interface with alpha_m (eq.
+// ECFlux_curv_2p) and subtracts the dissipation of eq. HOstable.
+
+template <int D, int K> struct Tile;
+template <> struct Tile<1, 0> { static constexpr int X = 256, Y = 1, Z = 1; };
+template <> struct Tile<2, 0> { static constexpr int X = 64, Y = 4, Z = 1; };
+template <> struct Tile<2, 1> { static constexpr int X = 16, Y = 16, Z = 1; };
+template <> struct Tile<3, 0> { static constexpr int X = 64, Y = 4, Z = 1; };
+template <> struct Tile<3, 1> { static constexpr int X = 16, Y = 16, Z = 1; };
+template <> struct Tile<3, 2> { static constexpr int X = 16, Y = 4, Z = 4; };
+
+// node data used by a pair flux (direction K)
+template <int D> struct Pq {
+  double rho, v[D], T, iT, g, iob, lr, lb, lt, m[D], mt;
+};
+
+template <int D, int K>
+__device__ __forceinline__ void load_pq(const Geo &G, const double *__restrict__ nd, long t, Pq<D> &q) {
+  using F = NF_<D>;
+  q.rho = nd[F::RHO * G.PN + t];
+#pragma unroll
+  for (int m = 0; m < D; ++m) q.v[m] = nd[(long)(F::V + m) * G.PN + t];
+  q.T = nd[F::T * G.PN + t];
+  q.iT = nd[F::IT * G.PN + t];
+  q.iob = nd[F::IOB * G.PN + t];
+  q.g = G.R * q.iob - G.a * q.rho * q.iT;  // g = R/(1 - b rho) - a rho/T
+  q.lr = nd[F::LNR * G.PN + t];
+  q.lb = nd[F::LNB * G.PN + t];
+  q.lt = nd[F::LNT * G.PN + t];
+#pragma unroll
+  for (int j = 0; j < D; ++j) q.m[j] = nd[(long)(F::MS + K * D + j) * G.PN + t];
+  q.mt = nd[(long)(F::XS + K) * G.PN + t];
+}
+
+// Two-point EC flux (eq. ECfluxMM with the closed-form U~, F~_j of Section 3.1), written in
+// contracted form: with the pair-averaged metrics mb, mbt and u = mbt + mb.v per node,
+//   F_rho = ({rho u} A + {g}{u})/D,  F_v = {v} F_rho + mb {rho}{T}{g},
+//   F_E = ({v/T}.F_v - K F_rho + a {rho u}{rho/T})/{1/T},
+// D = R/L(rho) + R b/L(1 - b rho) + R b/Pi - 2a/{T}, A = R b/Pi - a/{T},
+// K = {|v|^2/T}/2 - c_v {T}/L(T) + 2a{rho/T}; out[nv] receives {J dxi/dt}.
+template <int D>
+__device__ __forceinline__ void ec_pair(const Geo &G, const Pq<D> &l, const Pq<D> &r, double *out, unsigned &bad) {
+  double mb[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) mb[j] = 0.5 * (l.m[j] + r.m[j]);
+  double mbt = 0.5 * (l.mt + r.mt);
+  double ul = mbt, ur = mbt;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    ul += mb[j] * l.v[j];
+    ur += mb[j] * r.v[j];
+  }
+  double rhom = 0.5 * (l.rho + r.rho), Tm = 0.5 * (l.T + r.T), iTm = 0.5 * (l.iT + r.iT);
+  double rTm = 0.5 * (l.rho * l.iT + r.rho * r.iT), gm = 0.5 * (l.g + r.g);
+  double rum = 0.5 * (l.rho * ul + r.rho * ur), um = 0.5 * (ul + ur);
+  double Rb_Pi = G.R * G.b * l.iob * r.iob;
+  double iTmean = 2.0 / (l.T + r.T);
+  double Dd = G.R * inv_logmean(l.rho, r.rho, l.lr, r.lr) + Rb_Pi - 2.0 * G.a * iTmean;
+  if (G.b > 0.0) {
+    double obl = 1.0 - G.b * l.rho, obr = 1.0 - G.b * r.rho;
+    Dd += G.R * G.b * inv_logmean(obl, obr, l.lb, r.lb);
+  }
+  double A = Rb_Pi - G.a * iTmean;
+  double v2T = 0.0;
+#pragma unroll
+  for (int m = 0; m < D; ++m) v2T += l.v[m] * l.v[m] * l.iT + r.v[m] * r.v[m] * r.iT;
+  double Kk = 0.25 * v2T - G.cv * Tm * inv_logmean(l.T, r.T, l.lt, r.lt) + 2.0 * G.a * rTm;
+  if (!(Dd > 0.0)) bad = 1u;
+  double Fr = (rum * A + gm * um) / Dd;
+  double pt = rhom * Tm * gm;
+  double sum = 0.0;
+#pragma unroll
+  for (int m = 0; m < D; ++m) {
+    double Fv = 0.5 * (l.v[m] + r.v[m]) * Fr + mb[m] * pt;
+    out[1 + m] = Fv;
+    sum += 0.5 * (l.v[m] * l.iT + r.v[m] * r.iT) * Fv;
+  }
+  out[0] = Fr;
+  out[D + 1] = (sum - Kk * Fr + G.a * rum * rTm) / iTm;
+  out[D + 2] = mbt;
+}
+
+// interface eigen-system in the rotated frame
+template <int D> struct Eig {
+  double n[D], tg[D - 1 > 0 ? D - 1 : 1][D];  // normal and tangent rows of the rotation
+  double un, ut[D > 1 ? D - 1 : 1], H, c, c2G, s0, s1, st;
+};
+
+// scaled entropy variables W = R^T T V at one node
+template <int D>
+__device__ __forceinline__ void w_of(const Eig<D> &E, const double *V, double *W) {
+  double vn = 0.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) vn += E.n[j] * V[1 + j];
+  double vt[D > 1 ? D - 1 : 1];
+#pragma unroll
+  for (int t = 0; t < D - 1; ++t) {
+    vt[t] = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) vt[t] += E.tg[t][j] * V[1 + j];
+  }
+  double VE = V[D + 1];
+  double base = V[0] + E.un * vn + E.H * VE;
+#pragma unroll
+  for (int t = 0; t < D - 1; ++t) base += E.ut[t] * vt[t];
+  double ac = E.c * (vn + E.un * VE);
+  W[0] = E.s0 * (base - ac);
+  W[1] = E.s1 * (base - E.c2G * VE);
+#pragma unroll
+  for (int t = 0; t < D - 1; ++t) W[2 + t] = E.st * (vt[t] + E.ut[t] * VE);
+  W[D + 1] = E.s0 * (base + ac);
+}
+
+// magnitudes |R|^T |T V| of the terms summed into each W component (rounding scale of W)
+template <int D>
+__device__ __forceinline__ void wmag_of(const Eig<D> &E, const double *V, double *A) {
+  double vn = 0.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) vn += E.n[j] * V[1 + j];
+  double avt = 0.0, vt[D > 1 ? D - 1 : 1];
+#pragma unroll
+  for (int t = 0; t < D - 1; ++t) {
+    vt[t] = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) vt[t] += E.tg[t][j] * V[1 + j];
+    avt += fabs(E.ut[t]) * fabs(vt[t]);
+  }
+  double a0 = fabs(V[0]), an = fabs(vn), aE = fabs(V[D + 1]);
+  A[0] = E.s0 * (a0 + fabs(E.un - E.c) * an + avt + fabs(E.H - E.un * E.c) * aE);
+  A[1] = E.s1 * (a0 + fabs(E.un) * an + avt + fabs(E.H - E.c2G) * aE);
+#pragma unroll
+  for (int t = 0; t < D - 1; ++t) A[2 + t] = E.st * (fabs(vt[t]) + fabs(E.ut[t]) * aE);
+  A[D + 1] = E.s0 * (a0 + fabs(E.un + E.c) * an + avt + fabs(E.H + E.un * E.c) * aE);
+}
+
+// LDS doubles used by flux_tile for a TX x TY x TZ tile of interfaces normal to K
+template <int X_, int Y_, int Z_> struct TileShape { static constexpr int X = X_, Y = Y_, Z = Z_; };
+
+template <int D, int K, int TX, int TY, int TZ> struct FluxLds {
+  static constexpr int QX = TX + 2 * (K == 0), QY = TY + 2 * (K == 1), QZ = TZ + 2 * (K == 2);
+  static constexpr int Q = QX * QY * QZ;
+  static constexpr int SIZE = (D + 3) * 3 * Q;
+};
+
+// One 256-thread block computes the interface fluxes of the tile whose first interface is
+// (bx0, by0, bz0) and writes them to Fo (component-major, nif interfaces per component).
+// sP: FluxLds<...>::SIZE doubles of LDS.  Every thread reaches the internal barrier.
+template <int D, int K, int TX, int TY, int TZ>
+__device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict__ nd, double *__restrict__ Fo,
+                                          long nif, unsigned *flags, int bx0, int by0, int bz0,
+                                          double *__restrict__ sP) {
+  using F = NF_<D>;
+  static_assert(TX * TY * TZ == 256, "flux tiles map one interface to each of 256 threads");
+  using TL = TileShape<TX, TY, TZ>;
+  constexpr int NV = D + 2, NC = NV + 1;
+  using LQ = FluxLds<D, K, TX, TY, TZ>;
+  constexpr int QX = LQ::QX, QY = LQ::QY;
+  constexpr int Q = LQ::Q;
+  const int tid = threadIdx.x;
+  const long sK = K == 0 ? 1 : (K == 1 ? (long)G.P[0] : (long)G.P[0] * G.P[1]);
+  unsigned bad = 0;
+
+  // ---- phase 1: pair fluxes of the nodes owning pairs of this tile ----
+  for (int q = tid; q < Q; q += 256) {
+    int qx = q % QX, qy = (q / QX) % QY, qz = q / (QX * QY);
+    // node index: along K the first item is the node two below the tile's first left node
+    int i0 = bx0 + qx - (K == 0 ? 3 : 0), i1 = by0 + qy - (K == 1 ? 3 : 0), i2 = bz0 + qz - (K == 2 ? 3 : 0);
+    int ik = K == 0 ? i0 : (K == 1 ? i1 : i2);
+    bool ok = ik <= G.n[K] - 1 && (K == 0 || i0 < G.n[0]) && (K == 1 || i1 < G.n[1]) && (K == 2 || i2 < G.n[2]);
+    if (!ok) continue;
+    long pt = ((long)(i2 + G.g[2]) * G.P[1] + (i1 + G.g[1])) * G.P[0] + (i0 + G.g[0]);
+    Pq<D> a, b;
+    load_pq<D, K>(G, nd, pt, a);
+#pragma unroll
+    for (int m = 1; m <= 3; ++m) {
+      load_pq<D, K>(G, nd, pt + m * sK, b);
+      double o[NC];
+      ec_pair<D>(G, a, b, o, bad);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) sP[(c * 3 + (m - 1)) * Q + q] = o[c];
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 2: this thread's interface ----
+  const int tx = tid % TL::X, ty = (tid / TL::X) % TL::Y, tz = tid / (TL::X * TL::Y);
+  const int a0 = bx0 + tx, a1 = by0 + ty, a2 = bz0 + tz;  // interface index (along K: 0..n_K)
+  const int e0 = G.n[0] + (K == 0), e1 = G.n[1] + (K == 1), e2 = G.n[2] + (K == 2);
+  if (a0 >= e0 || a1 >= e1 || a2 >= e2) {
+    if (bad) raise_flag(flags, ESVDW_F_MEANCONSTRAINT);
+    return;
+  }
+  const int i0 = a0 - (K == 0), i1 = a1 - (K == 1), i2 = a2 - (K == 2);  // left node i
+  // LDS item of node i (local coordinates shifted by 2 along K)
+  const int qi = ((tz + 2 * (K == 2)) * QY + (ty + 2 * (K == 1))) * QX + (tx + 2 * (K == 0));
+  const int qs = K == 0 ? 1 : (K == 1 ? QX : QX * QY);
+  double Fl[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double *P1 = sP + (c * 3 + 0) * Q, *P2 = sP + (c * 3 + 1) * Q, *P3 = sP + (c * 3 + 2) * Q;
+    Fl[c] = AL1 * P1[qi] + AL2 * (P2[qi] + P2[qi - qs]) + AL3 * (P3[qi] + P3[qi - qs] + P3[qi - 2 * qs]);
+  }
+
+  if (G.diss) {
+    const long pc = ((long)(i2 + G.g[2]) * G.P[1] + (i1 + G.g[1])) * G.P[0] + (i0 + G.g[0]);
+    const long pr = pc + sK;
+    double rl = nd[F::RHO * G.PN + pc], rr = nd[F::RHO * G.PN + pr];
+    double pl = nd[F::P * G.PN + pc], pq = nd[F::P * G.PN + pr];
+    double ilr = inv_logmean(rl, rr, nd[F::LNR * G.PN + pc], nd[F::LNR * G.PN + pr]);
+    // rho/p and its logarithm
+    double zl = rl / pl, zr = rr / pq;
+    double ilz = inv_logmean(zl, zr, nd[F::LNR * G.PN + pc] - nd[F::LNP * G.PN + pc],
+                             nd[F::LNR * G.PN + pr] - nd[F::LNP * G.PN + pr]);
+    double rb = 1.0 / ilr;     // L(rho)
+    double pb = rb * ilz;      // L(rho)/L(rho/p)
+    double vb[D];
+#pragma unroll
+    for (int m = 0; m < D; ++m) vb[m] = 0.5 * (nd[(long)(F::V + m) * G.PN + pc] + nd[(long)(F::V + m) * G.PN + pr]);
+    double ob = 1.0 - G.b * rb;
+    double Tb = (pb + G.a * rb * rb) * ob * ilr * G.iR;
+    double iob = 1.0 / ob;
+    double c2 = (1.0 + G.delta) * G.R * Tb * iob * iob - 2.0 * G.a * rb;
+    double mm[D], L2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      mm[j] = 0.5 * (nd[(long)(F::MS + K * D + j) * G.PN + pc] + nd[(long)(F::MS + K * D + j) * G.PN + pr]);
+      L2 += mm[j] * mm[j];
+    }
+    double mtb = 0.5 * (nd[(long)(F::XS + K) * G.PN + pc] + nd[(long)(F::XS + K) * G.PN + pr]);
+    double L = sqrt(L2);
+    double iL = 1.0 / L;
+    Eig<D> E;
+#pragma unroll
+    for (int j = 0; j < D; ++j) E.n[j] = mm[j] * iL;
+    if constexpr (D == 2) {
+      E.tg[0][0] = -E.n[1];
+      E.tg[0][1] = E.n[0];
+    } else if constexpr (D == 3) {
+      double sxy = sqrt(E.n[0] * E.n[0] + E.n[1] * E.n[1]);
+      double ct = 1.0, st = 0.0;
+      if (sxy > 0.0) {
+        double is = 1.0 / sxy;
+        ct = E.n[0] * is;
+        st = E.n[1] * is;
+      }
+      E.tg[0][0] = -st;
+      E.tg[0][1] = ct;
+      E.tg[0][2] = 0.0;
+      E.tg[1][0] = -E.n[2] * ct;
+      E.tg[1][1] = -E.n[2] * st;
+      E.tg[1][2] = sxy;
+    }
+    double un = 0.0, vv = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      un += E.n[j] * vb[j];
+      vv += vb[j] * vb[j];
+    }
+    E.un = un;
+#pragma unroll
+    for (int t2 = 0; t2 < D - 1; ++t2) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) s += E.tg[t2][j] * vb[j];
+      E.ut[t2] = s;
+    }
+    double Eb = rb * (G.cv * Tb - G.a * rb) + 0.5 * rb * vv;
+    E.H = (Eb + pb) * ilr;
+    E.c = sqrt(c2);
+    E.c2G = c2 * G.cv * ob * G.iR;  // c^2 / Gamma with Gamma = R/(c_v (1 - b rho))
+    double ac = G.R * Tb - 2.0 * G.a * rb * ob * ob;
+    double ic2 = 1.0 / c2;
+    double S0 = 0.5 * rb * Tb * ic2, S1 = G.R * G.R * rb * Tb * Tb * ic2 / (G.cv * ac), St = rb * Tb;
+    if (!(S0 > 0.0) || !(S1 > 0.0)) bad = 1u;
+    E.s0 = sqrt(fabs(S0));
+    E.s1 = sqrt(fabs(S1));
+    E.st = sqrt(fabs(St));
+    double Lam = fmax(fabs(mtb + L * (un - E.c)), fmax(fabs(mtb + L * un), fabs(mtb + L * (un + E.c))));
+    double W[6][NV];
+    double A2[NV], A3[NV];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      double V[NV];
+      const long ps = pc + (s - 2) * sK;
+      {
+        double iT = nd[F::IT * G.PN + ps];
+        V[0] = nd[(long)F::V1 * G.PN + ps];
+#pragma unroll
+        for (int m = 0; m < D; ++m) V[1 + m] = nd[(long)(F::V + m) * G.PN + ps] * iT;
+        V[D + 1] = -iT;
+      }
+      w_of<D>(E, V, W[s]);
+      if (s == 2) wmag_of<D>(E, V, A2);
+      if (s == 3) wmag_of<D>(E, V, A3);
+    }
+    double y[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      double wm = mrweno5(G, W[0][c], W[1][c], W[2][c], W[3][c], W[4][c]);
+      double wp = mrweno5(G, W[5][c], W[4][c], W[3][c], W[2][c], W[1][c]);
+      double jr = wp - wm, j0 = W[3][c] - W[2][c];
+      // a plain jump below the rounding scale of W (2^-40 of its terms) counts as zero
+      if (fabs(j0) <= ldexp(A2[c] + A3[c], -40)) j0 = 0.0;
+      y[c] = ((jr > 0.0 && j0 > 0.0) || (jr < 0.0 && j0 < 0.0)) ? jr : 0.0;
+    }
+    // R y in the rotated frame, then rotate the momentum back (T^T)
+    double b0 = E.s0 * y[0], b1 = E.s1 * y[1], b2 = E.s0 * y[D + 1];
+    double dr = b0 + b1 + b2;
+    double dn = b0 * (un - E.c) + b1 * un + b2 * (un + E.c);
+    double dE = b0 * (E.H - un * E.c) + b1 * (E.H - E.c2G) + b2 * (E.H + un * E.c);
+    double dt_[D > 1 ? D - 1 : 1];
+#pragma unroll
+    for (int t2 = 0; t2 < D - 1; ++t2) {
+      dt_[t2] = E.ut[t2] * dr + E.st * y[2 + t2];
+      dE += E.st * y[2 + t2] * E.ut[t2];
+    }
+    double h = 0.5 * Lam;
+    Fl[0] -= h * dr;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      double mj = E.n[j] * dn;
+#pragma unroll
+      for (int t2 = 0; t2 < D - 1; ++t2) mj += E.tg[t2][j] * dt_[t2];
+      Fl[1 + j] -= h * mj;
+    }
+    Fl[D + 1] -= h * dE;
+  }
+  if (bad) raise_flag(flags, ESVDW_F_MEANCONSTRAINT);
+  const long ti = ((long)a2 * e1 + a1) * e0 + a0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) Fo[(long)c * nif + ti] = Fl[c];
+}
+
+
+// =============================== update ==========================================
+
+// mode 0: write dJU, dJ.  mode 1: SSP-RK3 stage s combination with dt from the device.
+template <int D>
+__device__ __forceinline__ void update_point(const Geo &G, const double *__restrict__ F0,
+                                             const double *__restrict__ F1, const double *__restrict__ F2, long nif0,
+                                             long nif1, long nif2, int mode, int s, const double *__restrict__ dtp,
+                                             const double *__restrict__ base_JU, const double *__restrict__ base_J,
+                                             const double *__restrict__ in_JU, const double *__restrict__ in_J,
+                                             double *__restrict__ out_JU, double *__restrict__ out_J, unsigned *flags,
+                                             int i0, int i1, int i2) {
+  constexpr int NV = D + 2;
+  const long t = lin(G, i0, i1, i2);
+  double L[NV + 1];
+#pragma unroll
+  for (int c = 0; c <= NV; ++c) L[c] = 0.0;
+  {  // direction 0: interfaces (i0 - 1/2) at a0 = i0 and (i0 + 1/2) at a0 = i0 + 1
+    long r = ((long)i2 * G.n[1] + i1) * (G.n[0] + 1) + i0;
+#pragma unroll
+    for (int c = 0; c <= NV; ++c) L[c] += (F0[(long)c * nif0 + r] - F0[(long)c * nif0 + r + 1]) * G.idxi[0];
+  }
+  if (D > 1) {
+    long r = ((long)i2 * (G.n[1] + 1) + i1) * G.n[0] + i0;
+#pragma unroll
+    for (int c = 0; c <= NV; ++c) L[c] += (F1[(long)c * nif1 + r] - F1[(long)c * nif1 + r + G.n[0]]) * G.idxi[1];
+  }
+  if (D > 2) {
+    long r = ((long)i2 * G.n[1] + i1) * G.n[0] + i0;
+    long st = (long)G.n[0] * G.n[1];
+#pragma unroll
+    for (int c = 0; c <= NV; ++c) L[c] += (F2[(long)c * nif2 + r] - F2[(long)c * nif2 + r + st]) * G.idxi[2];
+  }
+  bool nan = false;
+  if (mode == 0) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      out_JU[(long)c * G.N + t] = L[c];
+      nan |= isnan(L[c]);
+    }
+    out_J[t] = L[NV];
+    nan |= isnan(L[NV]);
+  } else {
+    double dt = *dtp;
+#pragma unroll
+    for (int c = 0; c <= NV; ++c) {
+      const double *inp = c < NV ? in_JU + (long)c * G.N : in_J;
+      const double *bp = c < NV ? base_JU + (long)c * G.N : base_J;
+      double y = inp[t] + dt * L[c];
+      double o;
+      if (s == 0) o = y;
+      else if (s == 1) o = 0.75 * bp[t] + 0.25 * y;
+      else o = (1.0 / 3.0) * bp[t] + (2.0 / 3.0) * y;
+      nan |= isnan(o);
+      if (c < NV) out_JU[(long)c * G.N + t] = o;
+      else out_J[t] = o;
+    }
+  }
+  if (nan) raise_flag(flags, ESVDW_F_NAN);
+}
+
+
+// =============================== CFL =============================================
+
+// CFL spectral-radius sum at node (i0, i1, i2): sum_k (|v . m_k| + |m_k| c) / (J dxi_k) with
+// m_k = J grad xi_k; metrics of the mesh x computed in place (1D/2D) or read from met (3D)
+template <int D>
+__device__ __forceinline__ double cfl_rate(const Geo &G, const double *__restrict__ JU, const double *__restrict__ J,
+                                           const double *__restrict__ x, const double *__restrict__ met, int i0,
+                                           int i1, int i2) {
+  const long t = lin(G, i0, i1, i2);
+  double s = 0.0;
+  double iJ = 1.0 / J[t];
+  double rho = JU[t] * iJ, v[D], v2 = 0.0;
+#pragma unroll
+  for (int m = 0; m < D; ++m) {
+    v[m] = JU[(long)(1 + m) * G.N + t] * iJ / rho;
+    v2 += v[m] * v[m];
+  }
+  double T = eos_T_rho_e(G, rho, JU[(long)(D + 1) * G.N + t] * iJ / rho - 0.5 * v2);
+  double c = sqrt(eos_c2(G, rho, T));
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    double L2 = 0.0, vn = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      double m;
+      if constexpr (D == 3) m = met[(long)(k * D + j) * G.N + t];
+      else m = metric_at<D>(G, x, nullptr, 0.0, nullptr, 0, k, j, i0, i1, i2);
+      L2 += m * m;
+      vn += m * v[j];
+    }
+    s += (fabs(vn) + sqrt(L2) * c) * iJ * G.idxi[k];
+  }
+  return s;
+}

@@ -19,7 +19,7 @@ MONVAR = {"rho": 0, "G": 1}
 # entry points declared in include/esvdw.h
 SYMBOLS = ["esvdw_create", "esvdw_destroy", "esvdw_get_status", "esvdw_strerror", "init_mesh", "init_state",
            "compute_metrics", "es_rhs", "rk_stage", "redistribute_mesh", "mesh_monitor", "mesh_jacobi",
-           "mesh_limiter", "cfl_dt", "esvdw_step", "esvdw_bench_kernel", "mlp_features", "mlp_infer",
+           "mesh_limiter", "mesh_converged", "cfl_dt", "esvdw_step", "esvdw_bench_kernel", "mlp_features", "mlp_infer",
            "mlp_grad", "mlp_adam"]
 MLP_NPARAM = 9360
 
@@ -92,6 +92,7 @@ def lib():
             "mesh_monitor": (I, [_VP] * 5),
             "mesh_jacobi": (I, [_VP, _VP, _VP, I, _VP, _VP]),
             "mesh_limiter": (I, [_VP] * 5),
+            "mesh_converged": (I, [_VP] * 3),
             "cfl_dt": (I, [_VP] * 6),
             "esvdw_step": (I, [_VP, _VP, _VP, _VP, I, _VP, _VP]),
             "esvdw_bench_kernel": (I, [_VP, I, I, _VP]),
@@ -195,6 +196,9 @@ class Context:
 
     def mesh_limiter(self, x_n, x_mu, gamma_dev, stream=None):
         _check(self.L.mesh_limiter(self.h, _ptr(x_n), _ptr(x_mu), _ptr(gamma_dev), _stream(stream)), "mesh_limiter")
+
+    def mesh_converged(self, xmu_out, stream=None):
+        _check(self.L.mesh_converged(self.h, _ptr(xmu_out), _stream(stream)), "mesh_converged")
 
     def cfl_dt(self, JU, J, x, dt_dev, stream=None):
         _check(self.L.cfl_dt(self.h, _ptr(JU), _ptr(J), _ptr(x), _ptr(dt_dev), _stream(stream)), "cfl_dt")
