@@ -42,7 +42,7 @@ def kernel_source_hash():
     """Hash of the sources the flux kernel is built from (the counters are void once they change)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("rhs.hip", "common.h"):
+    for f in ("rhs.hip", "scheme.h", "common.h"):
         with open(os.path.join(ROOT, "paper_2407_05568_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

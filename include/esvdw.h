@@ -42,6 +42,7 @@ extern "C" {
 #define ESVDW_F_MEANCONSTRAINT 2u /* D <= 0 (Theorem 3.1) or a non-positive S^2 entry */
 #define ESVDW_F_NAN 4u            /* a NaN reached an output */
 #define ESVDW_F_NOTCONVERGED 8u   /* tolerance-mode mesh iteration hit its sweep cap */
+#define ESVDW_F_BARRIER 16u       /* a batched stage kernel gave up waiting at a grid barrier */
 
 #define ESVDW_BC_PERIODIC 0
 #define ESVDW_BC_OUTFLOW 1 /* state: zero gradient; mesh: mirror about the boundary face */
@@ -194,6 +195,48 @@ int mlp_grad(esvdw_ctx *ctx, const float *feats, const float *targets, const int
 /* One Adam step (beta1 = 0.9, beta2 = 0.999, eps = 1e-8, bias-corrected at step >= 1) on the FP32
  * parameters with moment buffers m, v (MLP_NPARAM floats each, zero-initialised by the caller). */
 int mlp_adam(float *params, const float *grad, float *m, float *v, int step, float lr, hipStream_t stream);
+
+/* ---- Batched independent 2D problems ------------------------------------------------------
+ * A batch advances ninst independent 2D problems, each with its own esvdw_params (grid size,
+ * EOS constants R, c_v, a, b, boundary conditions, scheme parameters; dim must be 2), with one
+ * launch of a persistent kernel per SSP-RK3 stage for all of them (the scheme of Sections
+ * 3.1-3.3 at every node, the CFL step of Section 5 per instance).
+ * Caller arrays are pooled device arrays in FP64: instance i owns nodes [off[i], off[i+1]) and
+ * a pool with F fields stores instance i's fields contiguously from base + F off[i], in the
+ * single-problem layout ([field][y][x], N_i nodes per field).  Pools: x (2 fields), xdot (2),
+ * J (1), JU (4), prim (4: rho, v1, v2, p).  dt: ninst doubles. */
+typedef struct esvdw_batch esvdw_batch;
+
+/* Creates a batch (allocates its device scratch).  Returns ESVDW_EINVAL for an invalid or
+ * non-2D parameter set. */
+int esvdw_batch_create(int ninst, const esvdw_params *params, esvdw_batch **out);
+void esvdw_batch_destroy(esvdw_batch *b);
+/* Node offsets of the instances in the pools (off: ninst + 1 longs, may be NULL); returns the
+ * total node count. */
+long esvdw_batch_offsets(const esvdw_batch *b, long *off);
+/* Uniform meshes and their Jacobians for every instance (as init_mesh with uniform = 1). */
+int esvdw_batch_init_mesh(esvdw_batch *b, double *x, double *J, hipStream_t stream);
+/* Conserved variables JU = J U(prim) for every instance (as init_state). */
+int esvdw_batch_init_state(esvdw_batch *b, const double *prim, const double *J, double *JU, hipStream_t stream);
+/* One SSP-RK3 stage s of every instance, in the semantics of rk_stage: step base (JU0, J0),
+ * stage input (JUs, Js), output (JUout, Jout) (may alias the base but not the stage input).
+ * Stage 0 first computes each instance's CFL step dt[i] = cfl / max over nodes of the
+ * spectral-radius sum on (JU0, J0, x) (or dt_fixed) and stages 1, 2 read it.  xdot (may be
+ * NULL: fixed meshes) is the mesh velocity of the step: stage s uses the mesh x + c_s dt xdot,
+ * and stage 2 advances x in place to x + dt xdot. */
+int esvdw_batch_stage(esvdw_batch *b, int s, const double *JU0, const double *J0, const double *JUs,
+                      const double *Js, double *JUout, double *Jout, double *x, const double *xdot, double *dt,
+                      hipStream_t stream);
+/* One full SSP-RK3 step of every instance in place (three esvdw_batch_stage launches through
+ * the batch's own stage buffers); capturable in a HIP graph. */
+int esvdw_batch_step(esvdw_batch *b, double *JU, double *J, double *x, const double *xdot, double *dt,
+                     hipStream_t stream);
+/* Tile variants of the stage kernel (interface-tile shapes and blocks per CU): count, and the
+ * choice used by later launches (results are identical across variants; only speed differs). */
+int esvdw_batch_variants(void);
+int esvdw_batch_set_variant(esvdw_batch *b, int variant);
+/* Synchronises the device, copies the batch's status word (ESVDW_F_* bits) and clears it. */
+int esvdw_batch_get_status(esvdw_batch *b, unsigned *flags_host);
 
 #ifdef __cplusplus
 }

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libesvdw.so")
-SOURCES = ["api.hip", "rhs.hip", "mesh.hip", "mlp.hip"]
+SOURCES = ["api.hip", "rhs.hip", "mesh.hip", "mlp.hip", "batch.hip"]
 ARCH = os.environ.get("ESVDW_ARCH", "gfx950")
 
 

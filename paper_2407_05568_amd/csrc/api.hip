@@ -8,7 +8,7 @@
 
 #define HIPOK(x) ((x) == hipSuccess)
 
-static int valid(const esvdw_params *p) {
+int params_valid(const esvdw_params *p) {
   if (!p || p->dim < 1 || p->dim > 3) return 0;
   for (int k = 0; k < p->dim; ++k) {
     if (p->n[k] < 6) return 0;
@@ -23,7 +23,7 @@ static int valid(const esvdw_params *p) {
   return 1;
 }
 
-static void make_geo(const esvdw_params *p, Geo *G) {
+void make_geo(const esvdw_params *p, Geo *G) {
   memset(G, 0, sizeof(*G));
   G->dim = p->dim;
   G->nv = p->dim + 2;
@@ -87,7 +87,7 @@ void esvdw_destroy(esvdw_ctx *c) {
 int esvdw_create(const esvdw_params *p, esvdw_ctx **out) {
   if (!out) return ESVDW_EINVAL;
   *out = nullptr;
-  if (!valid(p)) return ESVDW_EINVAL;
+  if (!params_valid(p)) return ESVDW_EINVAL;
   esvdw_ctx *c = (esvdw_ctx *)calloc(1, sizeof(esvdw_ctx));
   if (!c) return ESVDW_EHIP;
   c->p = *p;

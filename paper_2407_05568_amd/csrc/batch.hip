@@ -1,0 +1,398 @@
+// batch.hip -- many independent 2D problems (each with its own grid size, EOS constants and
+// boundary conditions) advanced together: one launch of a persistent kernel per SSP-RK3
+// stage covers every instance.  Inside a stage, grid-wide barriers separate the phases
+//   [stage 0]  CFL spectral radius per node tile -> per-tile maxima, then dt per instance
+//   node data of every padded node of every instance
+//   interface fluxes of every instance, both directions
+//   flux differences and the RK combination (+ x^{n+1} = x^n + dt xdot at stage 2)
+// The work items of a phase are tiles listed instance by instance.  Workgroups are handed
+// to the 8 XCDs round-robin, so the blocks with equal blockIdx % 8 share one XCD; each such
+// group walks one contiguous eighth of the list, and neighbouring tiles (which read the same
+// node data) share that XCD's L2.
+#include <stdlib.h>
+#include <string.h>
+
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+#include "scheme.h"
+
+#define HIPOK(x) ((x) == hipSuccess)
+
+struct BInst {
+  Geo G;
+  long off;         // first node of the instance in the pooled arrays
+  double *nd;       // node buffer (NF_<2>::COUNT * PN)
+  double *F0, *F1;  // interface fluxes per direction ((nv + 1) * nif)
+  long nif0, nif1;
+  double cfl, dt_fixed;
+  int u0, u1;       // the instance's node tiles in the update list
+};
+
+struct BItem {
+  int inst, x0, y0, k;
+};
+
+// tile variants of the flux phase (direction 0 tile X0 x Y0, direction 1 tile X1 x Y1) and
+// blocks per CU requested from the compiler
+template <int V> struct BVar;
+template <> struct BVar<0> { static constexpr int X0 = 64, Y0 = 4, X1 = 16, Y1 = 16, OCC = 3; };
+template <> struct BVar<1> { static constexpr int X0 = 32, Y0 = 8, X1 = 16, Y1 = 16, OCC = 3; };
+template <> struct BVar<2> { static constexpr int X0 = 64, Y0 = 4, X1 = 32, Y1 = 8, OCC = 3; };
+template <> struct BVar<3> { static constexpr int X0 = 128, Y0 = 2, X1 = 8, Y1 = 32, OCC = 3; };
+template <> struct BVar<4> { static constexpr int X0 = 64, Y0 = 4, X1 = 16, Y1 = 16, OCC = 2; };
+#define BATCH_NVAR 5
+
+struct esvdw_batch {
+  int ninst, variant, dev;
+  int nblocks[BATCH_NVAR];
+  std::vector<Geo> geo;
+  std::vector<long> off;  // ninst + 1
+  std::vector<BInst> inst;
+  BInst *dI;
+  BItem *dNode, *dFlux, *dUpd;
+  int nNode, nFlux, nUpd;
+  double *nd_pool, *f_pool, *sAU, *sAJ, *sBU, *sBJ, *cpart;
+  unsigned *bar, *flags;
+};
+
+// ---- grid-wide barrier with a bounded wait ---------------------------------------------------
+// bar[0] counts arrivals, bar[1] is the generation.  Every thread fences its stores at device
+// scope before the block arrives and again after the release, so data written in one phase is
+// seen by every block (on every XCD) in the next.  A wait longer than about a second (the grid
+// was not co-resident) raises ESVDW_F_BARRIER and proceeds, so the kernel always terminates.
+#define BATCH_SPIN_LIMIT (1u << 24)
+
+__device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned nblocks, unsigned *flags) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned gen = __hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned arrived = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(bar + 1, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      unsigned spins = 0;
+      while (__hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > BATCH_SPIN_LIMIT) {
+          atomicOr(flags, ESVDW_F_BARRIER);
+          break;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  __threadfence();
+}
+
+// this block's share of n items: XCD x = blockIdx % 8 owns [x c, (x + 1) c), c = ceil(n / 8),
+// walked with stride gridDim / 8 (gridDim is a multiple of 8)
+#define XCD_WALK(n, it)                                                                              \
+  for (int it = (int)(blockIdx.x & 7u) * (((n) + 7) >> 3) + (int)(blockIdx.x >> 3),                  \
+           it##_end = min((n), ((int)(blockIdx.x & 7u) + 1) * (((n) + 7) >> 3));                      \
+       it < it##_end; it += (int)(gridDim.x >> 3))
+
+template <int X0, int Y0, int X1, int Y1, int OCC>
+__global__ void __launch_bounds__(256, OCC)
+    k_batch_stage(const BInst *__restrict__ I, int ninst, const BItem *__restrict__ inode, int nnode,
+                  const BItem *__restrict__ iflux, int nflux, const BItem *__restrict__ iupd, int nupd, int s,
+                  const double *__restrict__ bU, const double *__restrict__ bJ, const double *__restrict__ inU,
+                  const double *__restrict__ inJ, double *outU, double *outJ, double *x,
+                  const double *__restrict__ xd, double *dt, double *cpart, unsigned *bar, unsigned *flags) {
+  constexpr int L0 = FluxLds<2, 0, X0, Y0, 1>::SIZE, L1 = FluxLds<2, 1, X1, Y1, 1>::SIZE;
+  __shared__ double sP[L0 > L1 ? L0 : L1];
+  const unsigned nb = gridDim.x;
+  const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+
+  if (s == 0) {
+    // ---- CFL: per-tile maxima of the spectral-radius sum on (U^n, x^n) ----
+    XCD_WALK(nupd, it) {
+      const BItem w = iupd[it];
+      const BInst &B = I[w.inst];
+      const int i0 = w.x0 + tx, i1 = w.y0 + ty;
+      double r = 0.0;
+      if (i0 < B.G.n[0] && i1 < B.G.n[1])
+        r = cfl_rate<2>(B.G, bU + 4 * B.off, bJ + B.off, x + 2 * B.off, nullptr, i0, i1, 0);
+      double m = block_max(r);
+      if (tid == 0) cpart[it] = m;
+    }
+    grid_barrier(bar, nb, flags);
+    for (int i = blockIdx.x; i < ninst; i += nb) {
+      const BInst &B = I[i];
+      double m = 0.0;
+      for (int u = B.u0 + tid; u < B.u1; u += 256) m = fmax(m, cpart[u]);
+      m = block_max(m);
+      if (tid == 0) dt[i] = B.dt_fixed > 0.0 ? B.dt_fixed : B.cfl / m;
+    }
+  }
+
+  // ---- node data on the stage mesh x^n + c_s dt xdot ----
+  const double cs = s == 1 ? 1.0 : 0.5;
+  XCD_WALK(nnode, it) {
+    const BItem w = inode[it];
+    const BInst &B = I[w.inst];
+    const int p0 = w.x0 + tx, p1 = w.y0 + ty;
+    if (p0 < B.G.P[0] && p1 < B.G.P[1]) {
+      const double cdt = (xd && s > 0) ? cs * dt[w.inst] : 0.0;
+      node_point<2>(B.G, inU + 4 * B.off, inJ + B.off, nullptr, nullptr, x + 2 * B.off,
+                    xd ? xd + 2 * B.off : nullptr, cdt, nullptr, 0, B.nd, flags, p0, p1, 0);
+    }
+  }
+  grid_barrier(bar, nb, flags);
+
+  // ---- interface fluxes, both directions ----
+  XCD_WALK(nflux, it) {
+    const BItem w = iflux[it];
+    const BInst &B = I[w.inst];
+    if (w.k == 0) flux_tile<2, 0, X0, Y0, 1>(B.G, B.nd, B.F0, B.nif0, flags, w.x0, w.y0, 0, sP);
+    else flux_tile<2, 1, X1, Y1, 1>(B.G, B.nd, B.F1, B.nif1, flags, w.x0, w.y0, 0, sP);
+    __syncthreads();  // sP is reused by the next tile
+  }
+  grid_barrier(bar, nb, flags);
+
+  // ---- flux differences, RK combination, mesh advance ----
+  XCD_WALK(nupd, it) {
+    const BItem w = iupd[it];
+    const BInst &B = I[w.inst];
+    const int i0 = w.x0 + tx, i1 = w.y0 + ty;
+    if (i0 < B.G.n[0] && i1 < B.G.n[1]) {
+      update_point<2>(B.G, B.F0, B.F1, nullptr, B.nif0, B.nif1, 0, 1, s, dt + w.inst, bU + 4 * B.off, bJ + B.off,
+                      inU + 4 * B.off, inJ + B.off, outU + 4 * B.off, outJ + B.off, flags, i0, i1, 0);
+      if (s == 2 && xd) {
+        const long t = (long)i1 * B.G.n[0] + i0;
+        const double d = dt[w.inst];
+        for (int j = 0; j < 2; ++j) {
+          const long q = 2 * B.off + (long)j * B.G.N + t;
+          x[q] = x[q] + d * xd[q];
+        }
+      }
+    }
+  }
+}
+
+// ---- host side ---------------------------------------------------------------------------------
+
+template <int V> static int stage_blocks(int ncu) {
+  using C = BVar<V>;
+  int occ = 0;
+  if (!HIPOK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_stage<C::X0, C::Y0, C::X1, C::Y1, C::OCC>,
+                                                          256, 0)))
+    return 0;
+  int nb = ncu * occ;
+  return nb - nb % 8;
+}
+
+template <int V>
+static int launch_stage_v(esvdw_batch *b, int s, const double *bU, const double *bJ, const double *inU,
+                          const double *inJ, double *outU, double *outJ, double *x, const double *xd, double *dt,
+                          hipStream_t st) {
+  using C = BVar<V>;
+  hipLaunchKernelGGL((k_batch_stage<C::X0, C::Y0, C::X1, C::Y1, C::OCC>), dim3(b->nblocks[V]), dim3(256), 0, st,
+                     b->dI, b->ninst, b->dNode, b->nNode, b->dFlux, b->nFlux, b->dUpd, b->nUpd, s, bU, bJ, inU, inJ,
+                     outU, outJ, x, xd, dt, b->cpart, b->bar, b->flags);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+static int launch_stage(esvdw_batch *b, int s, const double *bU, const double *bJ, const double *inU,
+                        const double *inJ, double *outU, double *outJ, double *x, const double *xd, double *dt,
+                        hipStream_t st) {
+  switch (b->variant) {
+    case 0: return launch_stage_v<0>(b, s, bU, bJ, inU, inJ, outU, outJ, x, xd, dt, st);
+    case 1: return launch_stage_v<1>(b, s, bU, bJ, inU, inJ, outU, outJ, x, xd, dt, st);
+    case 2: return launch_stage_v<2>(b, s, bU, bJ, inU, inJ, outU, outJ, x, xd, dt, st);
+    case 3: return launch_stage_v<3>(b, s, bU, bJ, inU, inJ, outU, outJ, x, xd, dt, st);
+    default: return launch_stage_v<4>(b, s, bU, bJ, inU, inJ, outU, outJ, x, xd, dt, st);
+  }
+}
+
+template <int V> static void flux_items(const esvdw_batch *b, std::vector<BItem> &v) {
+  using C = BVar<V>;
+  v.clear();
+  for (int i = 0; i < b->ninst; ++i) {
+    const Geo &G = b->geo[i];
+    for (int y = 0; y < G.n[1]; y += C::Y0)
+      for (int x = 0; x < G.n[0] + 1; x += C::X0) v.push_back({i, x, y, 0});
+    for (int y = 0; y < G.n[1] + 1; y += C::Y1)
+      for (int x = 0; x < G.n[0]; x += C::X1) v.push_back({i, x, y, 1});
+  }
+}
+
+static int set_flux_items(esvdw_batch *b, int v) {
+  std::vector<BItem> items;
+  switch (v) {
+    case 0: flux_items<0>(b, items); break;
+    case 1: flux_items<1>(b, items); break;
+    case 2: flux_items<2>(b, items); break;
+    case 3: flux_items<3>(b, items); break;
+    default: flux_items<4>(b, items); break;
+  }
+  if (b->dFlux) (void)hipFree(b->dFlux);
+  b->dFlux = nullptr;
+  if (!HIPOK(hipMalloc((void **)&b->dFlux, items.size() * sizeof(BItem)))) return 0;
+  if (!HIPOK(hipMemcpy(b->dFlux, items.data(), items.size() * sizeof(BItem), hipMemcpyHostToDevice))) return 0;
+  b->nFlux = (int)items.size();
+  b->variant = v;
+  return 1;
+}
+
+template <typename T> static int balloc(T **p, size_t n) {
+  *p = nullptr;
+  return n == 0 ? 1 : HIPOK(hipMalloc((void **)p, n * sizeof(T)));
+}
+
+extern "C" {
+
+void esvdw_batch_destroy(esvdw_batch *b) {
+  if (!b) return;
+  void *bufs[] = {b->dI,  b->dNode, b->dFlux, b->dUpd, b->nd_pool, b->f_pool, b->sAU,
+                  b->sAJ, b->sBU,   b->sBJ,   b->cpart, b->bar,    b->flags};
+  for (void *p : bufs)
+    if (p) (void)hipFree(p);
+  delete b;
+}
+
+int esvdw_batch_create(int ninst, const esvdw_params *params, esvdw_batch **out) {
+  if (!out) return ESVDW_EINVAL;
+  *out = nullptr;
+  if (ninst < 1 || !params) return ESVDW_EINVAL;
+  for (int i = 0; i < ninst; ++i)
+    if (!params_valid(&params[i]) || params[i].dim != 2) return ESVDW_EINVAL;
+  esvdw_batch *b = new esvdw_batch();
+  b->ninst = ninst;
+  (void)hipGetDevice(&b->dev);
+  b->geo.resize(ninst);
+  b->off.assign(ninst + 1, 0);
+  b->inst.resize(ninst);
+  long nd_total = 0, f_total = 0;
+  std::vector<BItem> node_items, upd_items;
+  for (int i = 0; i < ninst; ++i) {
+    Geo &G = b->geo[i];
+    make_geo(&params[i], &G);
+    b->off[i + 1] = b->off[i] + G.N;
+    BInst &B = b->inst[i];
+    memset(&B, 0, sizeof(B));
+    B.G = G;
+    B.off = b->off[i];
+    B.nif0 = (long)(G.n[0] + 1) * G.n[1];
+    B.nif1 = (long)G.n[0] * (G.n[1] + 1);
+    B.cfl = params[i].cfl;
+    B.dt_fixed = params[i].dt_fixed;
+    nd_total += (long)NF_<2>::COUNT * G.PN;
+    f_total += 5 * (B.nif0 + B.nif1);
+    for (int y = 0; y < G.P[1]; y += 4)
+      for (int x = 0; x < G.P[0]; x += 64) node_items.push_back({i, x, y, 0});
+    B.u0 = (int)upd_items.size();
+    for (int y = 0; y < G.n[1]; y += 4)
+      for (int x = 0; x < G.n[0]; x += 64) upd_items.push_back({i, x, y, 0});
+    B.u1 = (int)upd_items.size();
+  }
+  const long total = b->off[ninst];
+  bool ok = balloc(&b->nd_pool, nd_total) && balloc(&b->f_pool, f_total) && balloc(&b->sAU, 4 * total) &&
+            balloc(&b->sAJ, total) && balloc(&b->sBU, 4 * total) && balloc(&b->sBJ, total) &&
+            balloc(&b->cpart, upd_items.size()) && balloc(&b->bar, 2) && balloc(&b->flags, 1) &&
+            balloc(&b->dI, ninst) && balloc(&b->dNode, node_items.size()) && balloc(&b->dUpd, upd_items.size());
+  if (ok) {
+    long nd_off = 0, f_off = 0;
+    for (int i = 0; i < ninst; ++i) {
+      BInst &B = b->inst[i];
+      B.nd = b->nd_pool + nd_off;
+      nd_off += (long)NF_<2>::COUNT * B.G.PN;
+      B.F0 = b->f_pool + f_off;
+      B.F1 = B.F0 + 5 * B.nif0;
+      f_off += 5 * (B.nif0 + B.nif1);
+    }
+    b->nNode = (int)node_items.size();
+    b->nUpd = (int)upd_items.size();
+    ok = HIPOK(hipMemcpy(b->dI, b->inst.data(), ninst * sizeof(BInst), hipMemcpyHostToDevice)) &&
+         HIPOK(hipMemcpy(b->dNode, node_items.data(), node_items.size() * sizeof(BItem), hipMemcpyHostToDevice)) &&
+         HIPOK(hipMemcpy(b->dUpd, upd_items.data(), upd_items.size() * sizeof(BItem), hipMemcpyHostToDevice)) &&
+         HIPOK(hipMemset(b->bar, 0, 2 * sizeof(unsigned))) && HIPOK(hipMemset(b->flags, 0, sizeof(unsigned)));
+  }
+  if (ok) {
+    int ncu = 0;
+    ok = HIPOK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->dev)) && ncu > 0;
+    if (ok) {
+      b->nblocks[0] = stage_blocks<0>(ncu);
+      b->nblocks[1] = stage_blocks<1>(ncu);
+      b->nblocks[2] = stage_blocks<2>(ncu);
+      b->nblocks[3] = stage_blocks<3>(ncu);
+      b->nblocks[4] = stage_blocks<4>(ncu);
+      for (int v = 0; v < BATCH_NVAR; ++v) ok = ok && b->nblocks[v] >= 8;
+    }
+  }
+  ok = ok && set_flux_items(b, 0) && HIPOK(hipDeviceSynchronize());
+  if (!ok) {
+    esvdw_batch_destroy(b);
+    return ESVDW_EHIP;
+  }
+  *out = b;
+  return ESVDW_OK;
+}
+
+long esvdw_batch_offsets(const esvdw_batch *b, long *off) {
+  if (!b) return -1;
+  if (off)
+    for (int i = 0; i <= b->ninst; ++i) off[i] = b->off[i];
+  return b->off[b->ninst];
+}
+
+int esvdw_batch_variants(void) { return BATCH_NVAR; }
+
+int esvdw_batch_set_variant(esvdw_batch *b, int v) {
+  if (!b || v < 0 || v >= BATCH_NVAR) return ESVDW_EINVAL;
+  if (v == b->variant) return ESVDW_OK;
+  if (!HIPOK(hipDeviceSynchronize())) return ESVDW_EHIP;
+  return set_flux_items(b, v) ? ESVDW_OK : ESVDW_EHIP;
+}
+
+int esvdw_batch_get_status(esvdw_batch *b, unsigned *flags_host) {
+  if (!b || !flags_host) return ESVDW_EINVAL;
+  if (!HIPOK(hipDeviceSynchronize())) return ESVDW_EHIP;
+  if (!HIPOK(hipMemcpy(flags_host, b->flags, sizeof(unsigned), hipMemcpyDeviceToHost))) return ESVDW_EHIP;
+  return HIPOK(hipMemset(b->flags, 0, sizeof(unsigned))) ? ESVDW_OK : ESVDW_EHIP;
+}
+
+int esvdw_batch_init_mesh(esvdw_batch *b, double *x, double *J, hipStream_t st) {
+  if (!b || !x || !J) return ESVDW_EINVAL;
+  for (int i = 0; i < b->ninst; ++i) {
+    esvdw_ctx c;
+    memset(&c, 0, sizeof(c));
+    c.G = b->geo[i];
+    if (launch_uniform_mesh(&c, x + 2 * b->off[i], st)) return ESVDW_EHIP;
+    if (launch_metrics(&c, x + 2 * b->off[i], nullptr, nullptr, nullptr, J + b->off[i], st)) return ESVDW_EHIP;
+  }
+  return ESVDW_OK;
+}
+
+int esvdw_batch_init_state(esvdw_batch *b, const double *prim, const double *J, double *JU, hipStream_t st) {
+  if (!b || !prim || !J || !JU) return ESVDW_EINVAL;
+  for (int i = 0; i < b->ninst; ++i) {
+    esvdw_ctx c;
+    memset(&c, 0, sizeof(c));
+    c.G = b->geo[i];
+    if (launch_init_state(&c, prim + 4 * b->off[i], J + b->off[i], JU + 4 * b->off[i], st)) return ESVDW_EHIP;
+  }
+  return ESVDW_OK;
+}
+
+int esvdw_batch_stage(esvdw_batch *b, int s, const double *JU0, const double *J0, const double *JUs,
+                      const double *Js, double *JUout, double *Jout, double *x, const double *xdot, double *dt,
+                      hipStream_t st) {
+  if (!b || s < 0 || s > 2 || !JU0 || !J0 || !JUs || !Js || !JUout || !Jout || !x || !dt) return ESVDW_EINVAL;
+  if (JUout == JUs || Jout == Js) return ESVDW_EINVAL;
+  return launch_stage(b, s, JU0, J0, JUs, Js, JUout, Jout, x, xdot, dt, st) ? ESVDW_EHIP : ESVDW_OK;
+}
+
+int esvdw_batch_step(esvdw_batch *b, double *JU, double *J, double *x, const double *xdot, double *dt,
+                     hipStream_t st) {
+  if (!b || !JU || !J || !x || !dt) return ESVDW_EINVAL;
+  if (launch_stage(b, 0, JU, J, JU, J, b->sAU, b->sAJ, x, xdot, dt, st)) return ESVDW_EHIP;
+  if (launch_stage(b, 1, JU, J, b->sAU, b->sAJ, b->sBU, b->sBJ, x, xdot, dt, st)) return ESVDW_EHIP;
+  if (launch_stage(b, 2, JU, J, b->sBU, b->sBJ, JU, J, x, xdot, dt, st)) return ESVDW_EHIP;
+  return ESVDW_OK;
+}
+
+}  // extern "C"

@@ -2,6 +2,9 @@
 #pragma once
 #include "common.h"
 
+int params_valid(const esvdw_params *p);
+void make_geo(const esvdw_params *p, Geo *G);
+
 int launch_dprod(esvdw_ctx *c, const double *xn, const double *xd, double cdt, hipStream_t st);
 int launch_metrics(esvdw_ctx *c, const double *x, const double *xd, double *met, double *xit, double *J,
                    hipStream_t st);

@@ -20,7 +20,9 @@ MONVAR = {"rho": 0, "G": 1}
 SYMBOLS = ["esvdw_create", "esvdw_destroy", "esvdw_get_status", "esvdw_strerror", "init_mesh", "init_state",
            "compute_metrics", "es_rhs", "rk_stage", "redistribute_mesh", "mesh_monitor", "mesh_jacobi",
            "mesh_limiter", "mesh_converged", "cfl_dt", "esvdw_step", "esvdw_bench_kernel", "mlp_features", "mlp_infer",
-           "mlp_grad", "mlp_adam"]
+           "mlp_grad", "mlp_adam", "esvdw_batch_create", "esvdw_batch_destroy", "esvdw_batch_offsets",
+           "esvdw_batch_init_mesh", "esvdw_batch_init_state", "esvdw_batch_stage", "esvdw_batch_step",
+           "esvdw_batch_variants", "esvdw_batch_set_variant", "esvdw_batch_get_status"]
 MLP_NPARAM = 9360
 
 
@@ -100,6 +102,16 @@ def lib():
             "mlp_infer": (I, [_VP] * 5),
             "mlp_grad": (I, [_VP, _VP, _VP, _VP, ctypes.c_long, ctypes.c_float, _VP, _VP, _VP, _VP]),
             "mlp_adam": (I, [_VP, _VP, _VP, _VP, I, ctypes.c_float, _VP]),
+            "esvdw_batch_create": (I, [I, ctypes.POINTER(Params), ctypes.POINTER(_VP)]),
+            "esvdw_batch_destroy": (None, [_VP]),
+            "esvdw_batch_offsets": (ctypes.c_long, [_VP, ctypes.POINTER(ctypes.c_long)]),
+            "esvdw_batch_init_mesh": (I, [_VP] * 4),
+            "esvdw_batch_init_state": (I, [_VP] * 5),
+            "esvdw_batch_stage": (I, [_VP, I] + [_VP] * 10),
+            "esvdw_batch_step": (I, [_VP] * 7),
+            "esvdw_batch_variants": (I, []),
+            "esvdw_batch_set_variant": (I, [_VP, I]),
+            "esvdw_batch_get_status": (I, [_VP, ctypes.POINTER(ctypes.c_uint)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -224,3 +236,57 @@ class Context:
 def mlp_adam(params, grad, m, v, step, lr, stream=None):
     _check(lib().mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr), _stream(stream)),
            "mlp_adam")
+
+
+class Batch:
+    """A batch of independent 2D problems (esvdw_batch_create); pooled arrays as documented in
+    the C header.  `problems` is a list of problem dicts (dim 2)."""
+
+    def __init__(self, problems):
+        self.L = lib()
+        self.n = len(problems)
+        arr = (Params * self.n)(*[params_from(p) for p in problems])
+        h = _VP()
+        _check(self.L.esvdw_batch_create(self.n, arr, ctypes.byref(h)), "esvdw_batch_create")
+        self.h = h
+        off = (ctypes.c_long * (self.n + 1))()
+        self.total = int(self.L.esvdw_batch_offsets(self.h, off))
+        self.off = [int(v) for v in off]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.esvdw_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def status(self):
+        f = ctypes.c_uint(0)
+        _check(self.L.esvdw_batch_get_status(self.h, ctypes.byref(f)), "esvdw_batch_get_status")
+        return f.value
+
+    def init_mesh(self, x, J, stream=None):
+        _check(self.L.esvdw_batch_init_mesh(self.h, _ptr(x), _ptr(J), _stream(stream)), "esvdw_batch_init_mesh")
+
+    def init_state(self, prim, J, JU, stream=None):
+        _check(self.L.esvdw_batch_init_state(self.h, _ptr(prim), _ptr(J), _ptr(JU), _stream(stream)),
+               "esvdw_batch_init_state")
+
+    def stage(self, s, JU0, J0, JUs, Js, JUout, Jout, x, xdot, dt, stream=None):
+        _check(self.L.esvdw_batch_stage(self.h, int(s), _ptr(JU0), _ptr(J0), _ptr(JUs), _ptr(Js), _ptr(JUout),
+                                        _ptr(Jout), _ptr(x), _ptr(xdot), _ptr(dt), _stream(stream)),
+               "esvdw_batch_stage")
+
+    def step(self, JU, J, x, xdot, dt, stream=None):
+        _check(self.L.esvdw_batch_step(self.h, _ptr(JU), _ptr(J), _ptr(x), _ptr(xdot), _ptr(dt), _stream(stream)),
+               "esvdw_batch_step")
+
+    def variants(self):
+        return int(self.L.esvdw_batch_variants())
+
+    def set_variant(self, v):
+        _check(self.L.esvdw_batch_set_variant(self.h, int(v)), "esvdw_batch_set_variant")

@@ -103,6 +103,18 @@ def _mean_ok(p, s1, s2):
     return R * Tm - 2.0 * a * rm * (1.0 - b * rm) ** 2 > 0
 
 
+def _logmean(u, v):
+    return u if abs(u - v) <= 1e-12 * abs(u) else (u - v) / (math.log(u) - math.log(v))
+
+
+def _avg_ok(p, s1, s2):
+    """The interface-averaged state of the dissipation (log-mean density, pressure
+    L(rho)/L(rho/p), Section 3.3) of two states (rho, T, p) is admissible."""
+    rb = _logmean(s1[0], s2[0])
+    pb = rb / _logmean(s1[0] / s1[2], s2[0] / s2[2])
+    return _admissible(p, rb, _T_of(p, rb, pb))
+
+
 # --- meshes ------------------------------------------------------------------------
 
 def smooth_mesh(p, seed, amp=0.02):
@@ -251,12 +263,14 @@ def riemann_1d_random(p, seed):
     return left, right
 
 
-def quadrant_states(p, seed, rho=(0.5, 1.5), pr=(0.8, 1.6), vmax=0.5):
+def quadrant_states(p, seed, rho=(0.5, 1.5), pr=(0.8, 1.6), vmax=0.5, strict=False, Tmin=0.0):
     """Four quadrant states of a 2D Riemann problem, drawn in reduced form:
     rho ~ U[0.5, 1.5] rho_c, p ~ U[0.8, 1.6] p_c, v_i ~ U[-0.5, 0.5] sqrt(p_c/rho_c) with |v| <= 0.5;
     inadmissible states and tuples whose edge-adjacent pairs break the mean-value constraint
-    are redrawn.  Returns a list of 4 tuples (rho, v1, v2, p) for quadrants
-    1 (x>1/2, y>1/2), 2 (x<1/2, y>1/2), 3 (x<1/2, y<1/2), 4 (x>1/2, y<1/2)."""
+    are redrawn; with strict=True also tuples where the dissipation's averaged state of an
+    edge-adjacent pair is inadmissible; states colder than Tmin T_c are redrawn too.  Returns a
+    list of 4 tuples (rho, v1, v2, p) for quadrants 1 (x>1/2, y>1/2), 2 (x<1/2, y>1/2),
+    3 (x<1/2, y<1/2), 4 (x>1/2, y<1/2)."""
     rng = np.random.default_rng(seed)
     rc, Tc, pc = _critical(p)
     vs = math.sqrt(pc / rc)
@@ -270,11 +284,15 @@ def quadrant_states(p, seed, rho=(0.5, 1.5), pr=(0.8, 1.6), vmax=0.5):
                 if np.hypot(*v) > vmax:
                     continue
                 T = _T_of(p, r, q)
-                if _admissible(p, r, T):
+                if _admissible(p, r, T) and T >= Tmin * Tc:
                     states.append((r, v[0] * vs, v[1] * vs, q, T))
                     break
         ok = all(_mean_ok(p, (states[i][0], states[i][4]), (states[(i + 1) % 4][0], states[(i + 1) % 4][4]))
                  for i in range(4))
+        if ok and strict:
+            ok = all(_avg_ok(p, (states[i][0], states[i][4], states[i][3]),
+                             (states[(i + 1) % 4][0], states[(i + 1) % 4][4], states[(i + 1) % 4][3]))
+                     for i in range(4))
         if ok:
             return [s[:4] for s in states]
 
@@ -313,7 +331,10 @@ def smooth_3d(p, seed, x=None):
 def batch_instances(seed, count=256, nmin=64, nmax=384):
     """Independent 2D Riemann instances: n ~ U{nmin..nmax} (square grids), a ~ U[2, 4],
     b ~ U[0.2, 0.4], R = 8/3, c_v = R/0.0125; quadrant states drawn in reduced form and
-    scaled by the instance's critical values (corresponding states)."""
+    scaled by the instance's critical values (corresponding states).  The states are kept
+    supercritical (T >= 1.05 T_c) with admissible averaged interface states: subcritical states
+    of the (rho, p) box near the spinodal curve send the first rarefactions of a quarter of the
+    instances out of the admissible set within one step."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(count):
@@ -321,6 +342,6 @@ def batch_instances(seed, count=256, nmin=64, nmax=384):
         a = float(rng.uniform(2.0, 4.0))
         b = float(rng.uniform(0.2, 0.4))
         p = problem(2, [n, n], bc="outflow", a=a, b=b)
-        st = quadrant_states(p, int(rng.integers(0, 2**31 - 1)))
+        st = quadrant_states(p, int(rng.integers(0, 2**31 - 1)), strict=True, Tmin=1.05)
         out.append((p, st))
     return out
