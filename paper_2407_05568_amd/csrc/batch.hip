@@ -1,11 +1,12 @@
 // batch.hip -- many independent 2D problems (each with its own grid size, EOS constants and
 // boundary conditions) advanced together: one launch of a persistent kernel per SSP-RK3
 // stage covers every instance.  Inside a stage, grid-wide barriers separate the phases
-//   [stage 0]  CFL spectral radius per node tile -> per-tile maxima, then dt per instance
+//   [stage 0]  CFL spectral radius per node chunk -> per-chunk maxima, then dt per instance
 //   node data of every padded node of every instance
 //   interface fluxes of every instance, both directions
 //   flux differences and the RK combination (+ x^{n+1} = x^n + dt xdot at stage 2)
-// The work items of a phase are tiles listed instance by instance.  Workgroups are handed
+// The work items of a phase (interface tiles, or chunks of 256 nodes) are listed instance by
+// instance.  Workgroups are handed
 // to the 8 XCDs round-robin, so the blocks with equal blockIdx % 8 share one XCD; each such
 // group walks one contiguous eighth of the list, and neighbouring tiles (which read the same
 // node data) share that XCD's L2.
@@ -27,9 +28,12 @@ struct BInst {
   double *F0, *F1;  // interface fluxes per direction ((nv + 1) * nif)
   long nif0, nif1;
   double cfl, dt_fixed;
-  int u0, u1;       // the instance's node tiles in the update list
+  int u0, u1;       // the instance's chunks in the update list
 };
 
+// a work item: a flux tile (first interface (x0, y0), direction k) or a chunk of 256
+// consecutive nodes starting at x0 (node data over the padded grid, CFL and update over the
+// interior); y0 unused for chunks
 struct BItem {
   int inst, x0, y0, k;
 };
@@ -37,11 +41,11 @@ struct BItem {
 // tile variants of the flux phase (direction 0 tile X0 x Y0, direction 1 tile X1 x Y1) and
 // blocks per CU requested from the compiler
 template <int V> struct BVar;
-template <> struct BVar<0> { static constexpr int X0 = 64, Y0 = 4, X1 = 16, Y1 = 16, OCC = 3; };
-template <> struct BVar<1> { static constexpr int X0 = 32, Y0 = 8, X1 = 16, Y1 = 16, OCC = 3; };
-template <> struct BVar<2> { static constexpr int X0 = 64, Y0 = 4, X1 = 32, Y1 = 8, OCC = 3; };
-template <> struct BVar<3> { static constexpr int X0 = 128, Y0 = 2, X1 = 8, Y1 = 32, OCC = 3; };
-template <> struct BVar<4> { static constexpr int X0 = 64, Y0 = 4, X1 = 16, Y1 = 16, OCC = 2; };
+template <> struct BVar<0> { static constexpr int X0 = 64, Y0 = 4, X1 = 16, Y1 = 16, OCC = 2; };
+template <> struct BVar<1> { static constexpr int X0 = 32, Y0 = 8, X1 = 16, Y1 = 16, OCC = 2; };
+template <> struct BVar<2> { static constexpr int X0 = 64, Y0 = 4, X1 = 32, Y1 = 8, OCC = 2; };
+template <> struct BVar<3> { static constexpr int X0 = 32, Y0 = 8, X1 = 8, Y1 = 32, OCC = 2; };
+template <> struct BVar<4> { static constexpr int X0 = 64, Y0 = 4, X1 = 16, Y1 = 16, OCC = 3; };
 #define BATCH_NVAR 5
 
 struct esvdw_batch {
@@ -105,17 +109,19 @@ __global__ void __launch_bounds__(256, OCC)
   constexpr int L0 = FluxLds<2, 0, X0, Y0, 1>::SIZE, L1 = FluxLds<2, 1, X1, Y1, 1>::SIZE;
   __shared__ double sP[L0 > L1 ? L0 : L1];
   const unsigned nb = gridDim.x;
-  const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+  const int tid = threadIdx.x;
 
   if (s == 0) {
-    // ---- CFL: per-tile maxima of the spectral-radius sum on (U^n, x^n) ----
+    // ---- CFL: per-chunk maxima of the spectral-radius sum on (U^n, x^n) ----
     XCD_WALK(nupd, it) {
       const BItem w = iupd[it];
       const BInst &B = I[w.inst];
-      const int i0 = w.x0 + tx, i1 = w.y0 + ty;
+      const int t = w.x0 + tid;
       double r = 0.0;
-      if (i0 < B.G.n[0] && i1 < B.G.n[1])
+      if (t < B.G.N) {
+        const int i1 = t / B.G.n[0], i0 = t - i1 * B.G.n[0];
         r = cfl_rate<2>(B.G, bU + 4 * B.off, bJ + B.off, x + 2 * B.off, nullptr, i0, i1, 0);
+      }
       double m = block_max(r);
       if (tid == 0) cpart[it] = m;
     }
@@ -134,8 +140,9 @@ __global__ void __launch_bounds__(256, OCC)
   XCD_WALK(nnode, it) {
     const BItem w = inode[it];
     const BInst &B = I[w.inst];
-    const int p0 = w.x0 + tx, p1 = w.y0 + ty;
-    if (p0 < B.G.P[0] && p1 < B.G.P[1]) {
+    const int t = w.x0 + tid;
+    if (t < B.G.PN) {
+      const int p1 = t / B.G.P[0], p0 = t - p1 * B.G.P[0];
       const double cdt = (xd && s > 0) ? cs * dt[w.inst] : 0.0;
       node_point<2>(B.G, inU + 4 * B.off, inJ + B.off, nullptr, nullptr, x + 2 * B.off,
                     xd ? xd + 2 * B.off : nullptr, cdt, nullptr, 0, B.nd, flags, p0, p1, 0);
@@ -157,12 +164,12 @@ __global__ void __launch_bounds__(256, OCC)
   XCD_WALK(nupd, it) {
     const BItem w = iupd[it];
     const BInst &B = I[w.inst];
-    const int i0 = w.x0 + tx, i1 = w.y0 + ty;
-    if (i0 < B.G.n[0] && i1 < B.G.n[1]) {
+    const int t = w.x0 + tid;
+    if (t < B.G.N) {
+      const int i1 = t / B.G.n[0], i0 = t - i1 * B.G.n[0];
       update_point<2>(B.G, B.F0, B.F1, nullptr, B.nif0, B.nif1, 0, 1, s, dt + w.inst, bU + 4 * B.off, bJ + B.off,
                       inU + 4 * B.off, inJ + B.off, outU + 4 * B.off, outJ + B.off, flags, i0, i1, 0);
       if (s == 2 && xd) {
-        const long t = (long)i1 * B.G.n[0] + i0;
         const double d = dt[w.inst];
         for (int j = 0; j < 2; ++j) {
           const long q = 2 * B.off + (long)j * B.G.N + t;
@@ -282,11 +289,9 @@ int esvdw_batch_create(int ninst, const esvdw_params *params, esvdw_batch **out)
     B.dt_fixed = params[i].dt_fixed;
     nd_total += (long)NF_<2>::COUNT * G.PN;
     f_total += 5 * (B.nif0 + B.nif1);
-    for (int y = 0; y < G.P[1]; y += 4)
-      for (int x = 0; x < G.P[0]; x += 64) node_items.push_back({i, x, y, 0});
+    for (long t = 0; t < G.PN; t += 256) node_items.push_back({i, (int)t, 0, 0});
     B.u0 = (int)upd_items.size();
-    for (int y = 0; y < G.n[1]; y += 4)
-      for (int x = 0; x < G.n[0]; x += 64) upd_items.push_back({i, x, y, 0});
+    for (long t = 0; t < G.N; t += 256) upd_items.push_back({i, (int)t, 0, 0});
     B.u1 = (int)upd_items.size();
   }
   const long total = b->off[ninst];

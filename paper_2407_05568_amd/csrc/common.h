@@ -140,6 +140,66 @@ __device__ __forceinline__ double metric_at(const Geo &G, const double *xn, cons
   return s * G.idxi[k1] * G.idxi[k2];
 }
 
+// 2D metrics m[k][j] = J dxi_k/dx_j at (i0, i1) on the stage mesh x_n + cdt xdot.  Nodes whose
+// whole stencil (3 nodes each way) is interior read the mesh directly, in the same arithmetic
+// order as delta_x; the others go through the boundary maps of mesh_at.  Keeping the common
+// case free of the boundary logic keeps the node kernels' code small.
+__device__ __forceinline__ void metrics2(const Geo &G, const double *__restrict__ xn, const double *__restrict__ xd,
+                                         double cdt, int i0, int i1, double m[2][2]) {
+  if (i0 >= 3 && i0 + 3 < G.n[0] && i1 >= 3 && i1 + 3 < G.n[1]) {
+    const double al[3] = {AL1, AL2, AL3};
+    const long t = (long)i1 * G.n[0] + i0, s1 = G.n[0];
+    const bool mv = xd && cdt != 0.0;
+    double d[2][2];  // d[q][r] = delta_q[x_r]
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const long e = q == 0 ? 1 : s1;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const double *xr = xn + (long)r * G.N, *vr = mv ? xd + (long)r * G.N : nullptr;
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 1; k <= 3; ++k) {
+          double p = xr[t + k * e], n = xr[t - k * e];
+          if (mv) {
+            p += cdt * vr[t + k * e];
+            n += cdt * vr[t - k * e];
+          }
+          acc += al[k - 1] * (p - n);
+        }
+        d[q][r] = 0.5 * acc;
+      }
+    }
+    // J dxi_1/dx_1 = x_2,xi2 ; J dxi_1/dx_2 = -x_1,xi2 ; J dxi_2/dx_1 = -x_2,xi1 ; J dxi_2/dx_2 = x_1,xi1
+    m[0][0] = d[1][1] * G.idxi[1];
+    m[0][1] = -d[1][0] * G.idxi[1];
+    m[1][0] = -d[0][1] * G.idxi[0];
+    m[1][1] = d[0][0] * G.idxi[0];
+    return;
+  }
+  // boundary nodes: one rolled loop over (q, r, k) keeps this rare path compact; the sums run
+  // over k = 1, 2, 3 in order, as in delta_x
+  double d00 = 0.0, d01 = 0.0, d10 = 0.0, d11 = 0.0;
+#pragma unroll 1
+  for (int it = 0; it < 12; ++it) {
+    const int q = it / 6, r = (it / 3) & 1, k = it % 3 + 1;
+    const int e0 = q == 0 ? k : 0, e1 = q == 1 ? k : 0;
+    const double c = (k == 1 ? AL1 : (k == 2 ? AL2 : AL3)) *
+                     (stage_x(G, xn, xd, cdt, r, i0 + e0, i1 + e1, 0) - stage_x(G, xn, xd, cdt, r, i0 - e0, i1 - e1, 0));
+    if (q == 0) {
+      if (r == 0) d00 += c;
+      else d01 += c;
+    } else {
+      if (r == 0) d10 += c;
+      else d11 += c;
+    }
+  }
+  m[0][0] = (0.5 * d11) * G.idxi[1];
+  m[0][1] = -(0.5 * d10) * G.idxi[1];
+  m[1][0] = -(0.5 * d01) * G.idxi[0];
+  m[1][1] = (0.5 * d00) * G.idxi[0];
+}
+
 // ---------------------------------------------------------------------------------
 // thermodynamics (eq. vdWEOS and the closed forms of Section 2, general units)
 // ---------------------------------------------------------------------------------

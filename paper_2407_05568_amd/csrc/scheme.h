@@ -94,13 +94,18 @@ __device__ __forceinline__ void node_point(const Geo &G, const double *__restric
     }
   } else {
     double m[D][D];
+    if constexpr (D == 2) {
+      metrics2(G, xn, xd, cdt, i0, i1, m);
+    } else {
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int j = 0; j < D; ++j) m[k][j] = metric_at<D>(G, xn, xd, cdt, dp, dpN, k, j, i0, i1, i2);
+    }
 #pragma unroll
     for (int k = 0; k < D; ++k)
 #pragma unroll
-      for (int j = 0; j < D; ++j) {
-        m[k][j] = metric_at<D>(G, xn, xd, cdt, dp, dpN, k, j, i0, i1, i2);
-        nd[(long)(F::MS + k * D + j) * G.PN + t] = m[k][j];
-      }
+      for (int j = 0; j < D; ++j) nd[(long)(F::MS + k * D + j) * G.PN + t] = m[k][j];
     double xv[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) xv[j] = xd ? mesh_at(G, xd, j, i0, i1, i2, 1) : 0.0;
@@ -534,14 +539,22 @@ __device__ __forceinline__ double cfl_rate(const Geo &G, const double *__restric
   }
   double T = eos_T_rho_e(G, rho, JU[(long)(D + 1) * G.N + t] * iJ / rho - 0.5 * v2);
   double c = sqrt(eos_c2(G, rho, T));
+  double mm[D][D];
+  if constexpr (D == 2) {
+    metrics2(G, x, nullptr, 0.0, i0, i1, mm);
+  } else {
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+        mm[k][j] = D == 3 ? met[(long)(k * D + j) * G.N + t] : metric_at<D>(G, x, nullptr, 0.0, nullptr, 0, k, j, i0, i1, i2);
+  }
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     double L2 = 0.0, vn = 0.0;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      double m;
-      if constexpr (D == 3) m = met[(long)(k * D + j) * G.N + t];
-      else m = metric_at<D>(G, x, nullptr, 0.0, nullptr, 0, k, j, i0, i1, i2);
+      const double m = mm[k][j];
       L2 += m * m;
       vn += m * v[j];
     }
