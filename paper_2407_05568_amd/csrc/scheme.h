@@ -321,13 +321,11 @@ __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict
   // LDS item of node i (local coordinates shifted by 2 along K)
   const int qi = ((tz + 2 * (K == 2)) * QY + (ty + 2 * (K == 1))) * QX + (tx + 2 * (K == 0));
   const int qs = K == 0 ? 1 : (K == 1 ? QX : QX * QY);
-  double Fl[NC];
+  // dissipation first (its projection dd, scaled by h, is subtracted from the EC flux at the
+  // end), so that the EC combination is not held in registers across it
+  double dd[NV], h = 0.0;
 #pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    const double *P1 = sP + (c * 3 + 0) * Q, *P2 = sP + (c * 3 + 1) * Q, *P3 = sP + (c * 3 + 2) * Q;
-    Fl[c] = AL1 * P1[qi] + AL2 * (P2[qi] + P2[qi - qs]) + AL3 * (P3[qi] + P3[qi - qs] + P3[qi - 2 * qs]);
-  }
-
+  for (int c = 0; c < NV; ++c) dd[c] = 0.0;
   if (G.diss) {
     const long pc = ((long)(i2 + G.g[2]) * G.P[1] + (i1 + G.g[1])) * G.P[0] + (i0 + G.g[0]);
     const long pr = pc + sK;
@@ -404,7 +402,7 @@ __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict
     E.st = sqrt(fabs(St));
     double Lam = fmax(fabs(mtb + L * (un - E.c)), fmax(fabs(mtb + L * un), fabs(mtb + L * (un + E.c))));
     double W[6][NV];
-    double A2[NV], A3[NV];
+    double As[NV];  // rounding scale of W at the two nodes of the interface
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
       double V[NV];
@@ -417,8 +415,13 @@ __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict
         V[D + 1] = -iT;
       }
       w_of<D>(E, V, W[s]);
-      if (s == 2) wmag_of<D>(E, V, A2);
-      if (s == 3) wmag_of<D>(E, V, A3);
+      if (s == 2) wmag_of<D>(E, V, As);
+      if (s == 3) {
+        double A3[NV];
+        wmag_of<D>(E, V, A3);
+#pragma unroll
+        for (int c = 0; c < NV; ++c) As[c] = As[c] + A3[c];
+      }
     }
     double y[NV];
 #pragma unroll
@@ -427,7 +430,7 @@ __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict
       double wp = mrweno5(G, W[5][c], W[4][c], W[3][c], W[2][c], W[1][c]);
       double jr = wp - wm, j0 = W[3][c] - W[2][c];
       // a plain jump below the rounding scale of W (2^-40 of its terms) counts as zero
-      if (fabs(j0) <= ldexp(A2[c] + A3[c], -40)) j0 = 0.0;
+      if (fabs(j0) <= ldexp(As[c], -40)) j0 = 0.0;
       y[c] = ((jr > 0.0 && j0 > 0.0) || (jr < 0.0 && j0 < 0.0)) ? jr : 0.0;
     }
     // R y in the rotated frame, then rotate the momentum back (T^T)
@@ -441,16 +444,23 @@ __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict
       dt_[t2] = E.ut[t2] * dr + E.st * y[2 + t2];
       dE += E.st * y[2 + t2] * E.ut[t2];
     }
-    double h = 0.5 * Lam;
-    Fl[0] -= h * dr;
+    h = 0.5 * Lam;
+    dd[0] = dr;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       double mj = E.n[j] * dn;
 #pragma unroll
       for (int t2 = 0; t2 < D - 1; ++t2) mj += E.tg[t2][j] * dt_[t2];
-      Fl[1 + j] -= h * mj;
+      dd[1 + j] = mj;
     }
-    Fl[D + 1] -= h * dE;
+    dd[D + 1] = dE;
+  }
+  double Fl[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double *P1 = sP + (c * 3 + 0) * Q, *P2 = sP + (c * 3 + 1) * Q, *P3 = sP + (c * 3 + 2) * Q;
+    Fl[c] = AL1 * P1[qi] + AL2 * (P2[qi] + P2[qi - qs]) + AL3 * (P3[qi] + P3[qi - qs] + P3[qi - 2 * qs]);
+    if (c < NV) Fl[c] -= h * dd[c];
   }
   if (bad) raise_flag(flags, ESVDW_F_MEANCONSTRAINT);
   const long ti = ((long)a2 * e1 + a1) * e0 + a0;
