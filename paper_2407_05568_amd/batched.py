@@ -1,9 +1,13 @@
 """Many independent 2D problems advanced together (esvdw_batch_*): set-up of a batch from
 problem dicts, the tile autotuner, and a throughput run.
 
-The autotuner times every tile variant of the persistent stage kernel on the batch it will
-run (a few full steps each, from the same initial state, HIP events on the launch stream) and
-keeps the fastest; the variants compute identical results, so the choice only moves speed.
+The library offers two launch modes over the same work lists and device code: a persistent
+kernel (one launch per RK stage, grid barriers between its phases) and phased kernels (CFL,
+node data, fluxes and update as separate launches, each at its own occupancy).  Variants
+0 .. V/2 - 1 are the persistent kernel with each tile set, V/2 .. V - 1 the phased kernels.  The
+autotuner times every variant on the batch it will run (a few full steps each, from the same
+initial state, HIP events on the launch stream) and keeps the fastest; the variants compute
+identical results, so the choice only moves speed.
 
 Run as a module for the 256-instance batch (prints one JSON line, progress on stderr):
     python -m paper_2407_05568_amd.batched --count 256 --steps 10
@@ -79,6 +83,11 @@ def autotune(run, steps=2):
     return best, times
 
 
+def launches_per_step(B, v):
+    """Kernel launches of one step: 3 for the persistent kernel, 2 + 3 x 3 for the phased ones."""
+    return 3 if v < B.variants() // 2 else 11
+
+
 def batch_problems(seed, count):
     inst = synth.batch_instances(seed, count)
     return [p for p, _ in inst], [synth.quadrants_2d(p, st) for p, st in inst]
@@ -122,7 +131,8 @@ def main():
     flags = run.B.status()
     out = {"metric": "FP64 node-stage updates/s, batched independent 2D problems", "value": 3 * nodes / (ms / 1e3),
            "unit": "node-stages/s", "ms_per_step": ms, "steps": args.steps, "instances": args.count, "nodes": nodes,
-           "variant": best, "variant_ms": times, "launches_per_step": 3, "status_flags": flags}
+           "variant": best, "mode": "persistent" if best < run.B.variants() // 2 else "phased",
+           "variant_ms": times, "launches_per_step": launches_per_step(run.B, best), "status_flags": flags}
     print(json.dumps(out), flush=True)
 
 

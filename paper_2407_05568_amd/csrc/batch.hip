@@ -46,11 +46,14 @@ template <> struct BVar<1> { static constexpr int X0 = 32, Y0 = 8, X1 = 16, Y1 =
 template <> struct BVar<2> { static constexpr int X0 = 64, Y0 = 4, X1 = 32, Y1 = 8, OCC = 2; };
 template <> struct BVar<3> { static constexpr int X0 = 32, Y0 = 8, X1 = 8, Y1 = 32, OCC = 2; };
 template <> struct BVar<4> { static constexpr int X0 = 64, Y0 = 4, X1 = 16, Y1 = 16, OCC = 3; };
-#define BATCH_NVAR 5
+#define BATCH_NTILE 5
+// variants 0 .. BATCH_NTILE - 1: the persistent kernel with tile set v; BATCH_NTILE .. 2 BATCH_NTILE - 1:
+// the phased kernels with tile set v - BATCH_NTILE
+#define BATCH_NVAR (2 * BATCH_NTILE)
 
 struct esvdw_batch {
   int ninst, variant, dev;
-  int nblocks[BATCH_NVAR];
+  int nblocks[BATCH_NTILE];
   std::vector<Geo> geo;
   std::vector<long> off;  // ninst + 1
   std::vector<BInst> inst;
@@ -99,6 +102,73 @@ __device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned nblocks, un
            it##_end = min((n), ((int)(blockIdx.x & 7u) + 1) * (((n) + 7) >> 3));                      \
        it < it##_end; it += (int)(gridDim.x >> 3))
 
+// ---- work items (shared by the persistent kernel and the phased kernels) -------------------
+
+// CFL rate of this thread's node of a 256-node chunk of the update list; block maximum to *out
+__device__ __forceinline__ void cfl_chunk(const BInst &B, int x0, const double *__restrict__ bU,
+                                          const double *__restrict__ bJ, const double *__restrict__ x, double *out) {
+  const int t = x0 + (int)threadIdx.x;
+  double r = 0.0;
+  if (t < B.G.N) {
+    const int i1 = t / B.G.n[0], i0 = t - i1 * B.G.n[0];
+    r = cfl_rate<2>(B.G, bU + 4 * B.off, bJ + B.off, x + 2 * B.off, nullptr, i0, i1, 0);
+  }
+  double m = block_max(r);
+  if (threadIdx.x == 0) *out = m;
+}
+
+// dt of one instance from its chunks' maxima (block-wide)
+__device__ __forceinline__ void dt_instance(const BInst &B, const double *__restrict__ cpart, double *dti) {
+  double m = 0.0;
+  for (int u = B.u0 + (int)threadIdx.x; u < B.u1; u += 256) m = fmax(m, cpart[u]);
+  m = block_max(m);
+  if (threadIdx.x == 0) *dti = B.dt_fixed > 0.0 ? B.dt_fixed : B.cfl / m;
+}
+
+// node data of this thread's padded node of a 256-node chunk, on the stage mesh x^n + c_s dt xdot
+__device__ __forceinline__ void node_chunk(const BInst &B, int inst, int x0, int s, const double *__restrict__ inU,
+                                           const double *__restrict__ inJ, const double *__restrict__ x,
+                                           const double *__restrict__ xd, const double *__restrict__ dt,
+                                           unsigned *flags) {
+  const int t = x0 + (int)threadIdx.x;
+  if (t < B.G.PN) {
+    const int p1 = t / B.G.P[0], p0 = t - p1 * B.G.P[0];
+    const double cdt = (xd && s > 0) ? (s == 1 ? 1.0 : 0.5) * dt[inst] : 0.0;
+    node_point<2>(B.G, inU + 4 * B.off, inJ + B.off, nullptr, nullptr, x + 2 * B.off, xd ? xd + 2 * B.off : nullptr,
+                  cdt, nullptr, 0, B.nd, flags, p0, p1, 0);
+  }
+}
+
+template <int X0, int Y0, int X1, int Y1>
+__device__ __forceinline__ void flux_item(const BInst &B, const BItem &w, unsigned *flags, double *sP) {
+  if (w.k == 0) flux_tile<2, 0, X0, Y0, 1>(B.G, B.nd, B.F0, B.nif0, flags, w.x0, w.y0, 0, sP);
+  else flux_tile<2, 1, X1, Y1, 1>(B.G, B.nd, B.F1, B.nif1, flags, w.x0, w.y0, 0, sP);
+}
+
+// flux differences and the RK combination at this thread's node of a chunk; at stage 2 with a
+// mesh velocity also x^{n+1} = x^n + dt xdot
+__device__ __forceinline__ void update_chunk(const BInst &B, int inst, int x0, int s, const double *__restrict__ bU,
+                                             const double *__restrict__ bJ, const double *__restrict__ inU,
+                                             const double *__restrict__ inJ, double *outU, double *outJ, double *x,
+                                             const double *__restrict__ xd, const double *__restrict__ dt,
+                                             unsigned *flags) {
+  const int t = x0 + (int)threadIdx.x;
+  if (t < B.G.N) {
+    const int i1 = t / B.G.n[0], i0 = t - i1 * B.G.n[0];
+    update_point<2>(B.G, B.F0, B.F1, nullptr, B.nif0, B.nif1, 0, 1, s, dt + inst, bU + 4 * B.off, bJ + B.off,
+                    inU + 4 * B.off, inJ + B.off, outU + 4 * B.off, outJ + B.off, flags, i0, i1, 0);
+    if (s == 2 && xd) {
+      const double d = dt[inst];
+      for (int j = 0; j < 2; ++j) {
+        const long q = 2 * B.off + (long)j * B.G.N + t;
+        x[q] = x[q] + d * xd[q];
+      }
+    }
+  }
+}
+
+// ---- the persistent stage kernel: one launch per RK stage -----------------------------------
+
 template <int X0, int Y0, int X1, int Y1, int OCC>
 __global__ void __launch_bounds__(256, OCC)
     k_batch_stage(const BInst *__restrict__ I, int ninst, const BItem *__restrict__ inode, int nnode,
@@ -109,75 +179,85 @@ __global__ void __launch_bounds__(256, OCC)
   constexpr int L0 = FluxLds<2, 0, X0, Y0, 1>::SIZE, L1 = FluxLds<2, 1, X1, Y1, 1>::SIZE;
   __shared__ double sP[L0 > L1 ? L0 : L1];
   const unsigned nb = gridDim.x;
-  const int tid = threadIdx.x;
-
   if (s == 0) {
-    // ---- CFL: per-chunk maxima of the spectral-radius sum on (U^n, x^n) ----
     XCD_WALK(nupd, it) {
       const BItem w = iupd[it];
-      const BInst &B = I[w.inst];
-      const int t = w.x0 + tid;
-      double r = 0.0;
-      if (t < B.G.N) {
-        const int i1 = t / B.G.n[0], i0 = t - i1 * B.G.n[0];
-        r = cfl_rate<2>(B.G, bU + 4 * B.off, bJ + B.off, x + 2 * B.off, nullptr, i0, i1, 0);
-      }
-      double m = block_max(r);
-      if (tid == 0) cpart[it] = m;
+      cfl_chunk(I[w.inst], w.x0, bU, bJ, x, cpart + it);
     }
     grid_barrier(bar, nb, flags);
-    for (int i = blockIdx.x; i < ninst; i += nb) {
-      const BInst &B = I[i];
-      double m = 0.0;
-      for (int u = B.u0 + tid; u < B.u1; u += 256) m = fmax(m, cpart[u]);
-      m = block_max(m);
-      if (tid == 0) dt[i] = B.dt_fixed > 0.0 ? B.dt_fixed : B.cfl / m;
-    }
+    for (int i = blockIdx.x; i < ninst; i += nb) dt_instance(I[i], cpart, dt + i);
   }
-
-  // ---- node data on the stage mesh x^n + c_s dt xdot ----
-  const double cs = s == 1 ? 1.0 : 0.5;
   XCD_WALK(nnode, it) {
     const BItem w = inode[it];
-    const BInst &B = I[w.inst];
-    const int t = w.x0 + tid;
-    if (t < B.G.PN) {
-      const int p1 = t / B.G.P[0], p0 = t - p1 * B.G.P[0];
-      const double cdt = (xd && s > 0) ? cs * dt[w.inst] : 0.0;
-      node_point<2>(B.G, inU + 4 * B.off, inJ + B.off, nullptr, nullptr, x + 2 * B.off,
-                    xd ? xd + 2 * B.off : nullptr, cdt, nullptr, 0, B.nd, flags, p0, p1, 0);
-    }
+    node_chunk(I[w.inst], w.inst, w.x0, s, inU, inJ, x, xd, dt, flags);
   }
   grid_barrier(bar, nb, flags);
-
-  // ---- interface fluxes, both directions ----
   XCD_WALK(nflux, it) {
     const BItem w = iflux[it];
-    const BInst &B = I[w.inst];
-    if (w.k == 0) flux_tile<2, 0, X0, Y0, 1>(B.G, B.nd, B.F0, B.nif0, flags, w.x0, w.y0, 0, sP);
-    else flux_tile<2, 1, X1, Y1, 1>(B.G, B.nd, B.F1, B.nif1, flags, w.x0, w.y0, 0, sP);
+    flux_item<X0, Y0, X1, Y1>(I[w.inst], w, flags, sP);
     __syncthreads();  // sP is reused by the next tile
   }
   grid_barrier(bar, nb, flags);
-
-  // ---- flux differences, RK combination, mesh advance ----
   XCD_WALK(nupd, it) {
     const BItem w = iupd[it];
-    const BInst &B = I[w.inst];
-    const int t = w.x0 + tid;
-    if (t < B.G.N) {
-      const int i1 = t / B.G.n[0], i0 = t - i1 * B.G.n[0];
-      update_point<2>(B.G, B.F0, B.F1, nullptr, B.nif0, B.nif1, 0, 1, s, dt + w.inst, bU + 4 * B.off, bJ + B.off,
-                      inU + 4 * B.off, inJ + B.off, outU + 4 * B.off, outJ + B.off, flags, i0, i1, 0);
-      if (s == 2 && xd) {
-        const double d = dt[w.inst];
-        for (int j = 0; j < 2; ++j) {
-          const long q = 2 * B.off + (long)j * B.G.N + t;
-          x[q] = x[q] + d * xd[q];
-        }
-      }
-    }
+    update_chunk(I[w.inst], w.inst, w.x0, s, bU, bJ, inU, inJ, outU, outJ, x, xd, dt, flags);
   }
+}
+
+// ---- the phased kernels: the same items, one launch per phase --------------------------------
+// Each launch gives each phase its own occupancy.  Grid = 8 ceil(n / 8) blocks; block b takes
+// item (b % 8) ceil(n / 8) + b / 8, so each XCD takes a contiguous eighth of the list.
+__device__ __forceinline__ int xcd_item(int n) {
+  const int c = (n + 7) >> 3, j = (int)(blockIdx.x >> 3), it = (int)(blockIdx.x & 7u) * c + j;
+  return (j < c && it < n) ? it : -1;
+}
+
+__global__ void __launch_bounds__(256) k_bph_cfl(const BInst *__restrict__ I, const BItem *__restrict__ iupd, int nupd,
+                                                 const double *__restrict__ bU, const double *__restrict__ bJ,
+                                                 const double *__restrict__ x, double *cpart) {
+  const int it = xcd_item(nupd);
+  if (it < 0) return;
+  const BItem w = iupd[it];
+  cfl_chunk(I[w.inst], w.x0, bU, bJ, x, cpart + it);
+}
+
+__global__ void __launch_bounds__(256) k_bph_dt(const BInst *__restrict__ I, const double *__restrict__ cpart,
+                                                double *dt) {
+  dt_instance(I[blockIdx.x], cpart, dt + blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_bph_nodes(const BInst *__restrict__ I, const BItem *__restrict__ inode,
+                                                   int nnode, int s, const double *__restrict__ inU,
+                                                   const double *__restrict__ inJ, const double *__restrict__ x,
+                                                   const double *__restrict__ xd, const double *__restrict__ dt,
+                                                   unsigned *flags) {
+  const int it = xcd_item(nnode);
+  if (it < 0) return;
+  const BItem w = inode[it];
+  node_chunk(I[w.inst], w.inst, w.x0, s, inU, inJ, x, xd, dt, flags);
+}
+
+template <int X0, int Y0, int X1, int Y1, int OCC>
+__global__ void __launch_bounds__(256, OCC) k_bph_flux(const BInst *__restrict__ I, const BItem *__restrict__ iflux,
+                                                       int nflux, unsigned *flags) {
+  constexpr int L0 = FluxLds<2, 0, X0, Y0, 1>::SIZE, L1 = FluxLds<2, 1, X1, Y1, 1>::SIZE;
+  __shared__ double sP[L0 > L1 ? L0 : L1];
+  const int it = xcd_item(nflux);
+  if (it < 0) return;
+  const BItem w = iflux[it];
+  flux_item<X0, Y0, X1, Y1>(I[w.inst], w, flags, sP);
+}
+
+__global__ void __launch_bounds__(256) k_bph_update(const BInst *__restrict__ I, const BItem *__restrict__ iupd,
+                                                    int nupd, int s, const double *__restrict__ bU,
+                                                    const double *__restrict__ bJ, const double *__restrict__ inU,
+                                                    const double *__restrict__ inJ, double *outU, double *outJ,
+                                                    double *x, const double *__restrict__ xd,
+                                                    const double *__restrict__ dt, unsigned *flags) {
+  const int it = xcd_item(nupd);
+  if (it < 0) return;
+  const BItem w = iupd[it];
+  update_chunk(I[w.inst], w.inst, w.x0, s, bU, bJ, inU, inJ, outU, outJ, x, xd, dt, flags);
 }
 
 // ---- host side ---------------------------------------------------------------------------------
@@ -203,6 +283,27 @@ static int launch_stage_v(esvdw_batch *b, int s, const double *bU, const double 
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+static inline unsigned xcd_grid(int n) { return 8u * (unsigned)((n + 7) / 8); }
+
+template <int V>
+static int launch_phased_v(esvdw_batch *b, int s, const double *bU, const double *bJ, const double *inU,
+                           const double *inJ, double *outU, double *outJ, double *x, const double *xd, double *dt,
+                           hipStream_t st) {
+  using C = BVar<V>;
+  if (s == 0) {
+    hipLaunchKernelGGL(k_bph_cfl, dim3(xcd_grid(b->nUpd)), dim3(256), 0, st, b->dI, b->dUpd, b->nUpd, bU, bJ, x,
+                       b->cpart);
+    hipLaunchKernelGGL(k_bph_dt, dim3(b->ninst), dim3(256), 0, st, b->dI, b->cpart, dt);
+  }
+  hipLaunchKernelGGL(k_bph_nodes, dim3(xcd_grid(b->nNode)), dim3(256), 0, st, b->dI, b->dNode, b->nNode, s, inU, inJ,
+                     x, xd, dt, b->flags);
+  hipLaunchKernelGGL((k_bph_flux<C::X0, C::Y0, C::X1, C::Y1, C::OCC>), dim3(xcd_grid(b->nFlux)), dim3(256), 0, st,
+                     b->dI, b->dFlux, b->nFlux, b->flags);
+  hipLaunchKernelGGL(k_bph_update, dim3(xcd_grid(b->nUpd)), dim3(256), 0, st, b->dI, b->dUpd, b->nUpd, s, bU, bJ,
+                     inU, inJ, outU, outJ, x, xd, dt, b->flags);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 static int launch_stage(esvdw_batch *b, int s, const double *bU, const double *bJ, const double *inU,
                         const double *inJ, double *outU, double *outJ, double *x, const double *xd, double *dt,
                         hipStream_t st) {
@@ -211,7 +312,12 @@ static int launch_stage(esvdw_batch *b, int s, const double *bU, const double *b
     case 1: return launch_stage_v<1>(b, s, bU, bJ, inU, inJ, outU, outJ, x, xd, dt, st);
     case 2: return launch_stage_v<2>(b, s, bU, bJ, inU, inJ, outU, outJ, x, xd, dt, st);
     case 3: return launch_stage_v<3>(b, s, bU, bJ, inU, inJ, outU, outJ, x, xd, dt, st);
-    default: return launch_stage_v<4>(b, s, bU, bJ, inU, inJ, outU, outJ, x, xd, dt, st);
+    case 4: return launch_stage_v<4>(b, s, bU, bJ, inU, inJ, outU, outJ, x, xd, dt, st);
+    case 5: return launch_phased_v<0>(b, s, bU, bJ, inU, inJ, outU, outJ, x, xd, dt, st);
+    case 6: return launch_phased_v<1>(b, s, bU, bJ, inU, inJ, outU, outJ, x, xd, dt, st);
+    case 7: return launch_phased_v<2>(b, s, bU, bJ, inU, inJ, outU, outJ, x, xd, dt, st);
+    case 8: return launch_phased_v<3>(b, s, bU, bJ, inU, inJ, outU, outJ, x, xd, dt, st);
+    default: return launch_phased_v<4>(b, s, bU, bJ, inU, inJ, outU, outJ, x, xd, dt, st);
   }
 }
 
@@ -229,7 +335,7 @@ template <int V> static void flux_items(const esvdw_batch *b, std::vector<BItem>
 
 static int set_flux_items(esvdw_batch *b, int v) {
   std::vector<BItem> items;
-  switch (v) {
+  switch (v % BATCH_NTILE) {
     case 0: flux_items<0>(b, items); break;
     case 1: flux_items<1>(b, items); break;
     case 2: flux_items<2>(b, items); break;
@@ -325,7 +431,7 @@ int esvdw_batch_create(int ninst, const esvdw_params *params, esvdw_batch **out)
       b->nblocks[2] = stage_blocks<2>(ncu);
       b->nblocks[3] = stage_blocks<3>(ncu);
       b->nblocks[4] = stage_blocks<4>(ncu);
-      for (int v = 0; v < BATCH_NVAR; ++v) ok = ok && b->nblocks[v] >= 8;
+      for (int v = 0; v < BATCH_NTILE; ++v) ok = ok && b->nblocks[v] >= 8;
     }
   }
   ok = ok && set_flux_items(b, 0) && HIPOK(hipDeviceSynchronize());
