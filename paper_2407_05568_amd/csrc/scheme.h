@@ -263,10 +263,14 @@ __device__ __forceinline__ void wmag_of(const Eig<D> &E, const double *V, double
 // LDS doubles used by flux_tile for a TX x TY x TZ tile of interfaces normal to K
 template <int X_, int Y_, int Z_> struct TileShape { static constexpr int X = X_, Y = Y_, Z = Z_; };
 
+// (pair fluxes of the nodes owning pairs, then the entropy-variable inputs V_1, v, 1/T of the
+// dissipation stencils: the tile's nodes along K with 3 more on the low side and 2 on the high)
 template <int D, int K, int TX, int TY, int TZ> struct FluxLds {
   static constexpr int QX = TX + 2 * (K == 0), QY = TY + 2 * (K == 1), QZ = TZ + 2 * (K == 2);
   static constexpr int Q = QX * QY * QZ;
-  static constexpr int SIZE = (D + 3) * 3 * Q;
+  static constexpr int WX = TX + 5 * (K == 0), WY = TY + 5 * (K == 1), WZ = TZ + 5 * (K == 2);
+  static constexpr int W = WX * WY * WZ;
+  static constexpr int SIZE = (D + 3) * 3 * Q + (D + 2) * W;
 };
 
 // One 256-thread block computes the interface fluxes of the tile whose first interface is
@@ -283,6 +287,8 @@ __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict
   using LQ = FluxLds<D, K, TX, TY, TZ>;
   constexpr int QX = LQ::QX, QY = LQ::QY;
   constexpr int Q = LQ::Q;
+  constexpr int WX = LQ::WX, WY = LQ::WY, QW = LQ::W;
+  double *__restrict__ sV = sP + NC * 3 * Q;  // [V_1, v_1..v_D, 1/T][QW]
   const int tid = threadIdx.x;
   const long sK = K == 0 ? 1 : (K == 1 ? (long)G.P[0] : (long)G.P[0] * G.P[1]);
   unsigned bad = 0;
@@ -305,6 +311,21 @@ __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict
       ec_pair<D>(G, a, b, o, bad);
 #pragma unroll
       for (int c = 0; c < NC; ++c) sP[(c * 3 + (m - 1)) * Q + q] = o[c];
+    }
+  }
+  if (G.diss) {
+    for (int q = tid; q < QW; q += 256) {
+      int qx = q % WX, qy = (q / WX) % WY, qz = q / (WX * WY);
+      int i0 = bx0 + qx - (K == 0 ? 3 : 0), i1 = by0 + qy - (K == 1 ? 3 : 0), i2 = bz0 + qz - (K == 2 ? 3 : 0);
+      int ik = K == 0 ? i0 : (K == 1 ? i1 : i2);
+      // the node buffer holds 3 ghost layers: node indices -3 .. n_K + 2 along K
+      bool ok = ik <= G.n[K] + 2 && (K == 0 || i0 < G.n[0]) && (K == 1 || i1 < G.n[1]) && (K == 2 || i2 < G.n[2]);
+      if (!ok) continue;
+      long pt = ((long)(i2 + G.g[2]) * G.P[1] + (i1 + G.g[1])) * G.P[0] + (i0 + G.g[0]);
+      sV[q] = nd[(long)F::V1 * G.PN + pt];
+#pragma unroll
+      for (int m = 0; m < D; ++m) sV[(1 + m) * QW + q] = nd[(long)(F::V + m) * G.PN + pt];
+      sV[(D + 1) * QW + q] = nd[(long)F::IT * G.PN + pt];
     }
   }
   __syncthreads();
@@ -403,15 +424,17 @@ __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict
     double Lam = fmax(fabs(mtb + L * (un - E.c)), fmax(fabs(mtb + L * un), fabs(mtb + L * (un + E.c))));
     double W[6][NV];
     double As[NV];  // rounding scale of W at the two nodes of the interface
+    // LDS item of node (interface - 3) along K: local coordinates (tx, ty, tz)
+    const int qw0 = (tz * WY + ty) * WX + tx, qws = K == 0 ? 1 : (K == 1 ? WX : WX * WY);
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
       double V[NV];
-      const long ps = pc + (s - 2) * sK;
+      const int qw = qw0 + s * qws;
       {
-        double iT = nd[F::IT * G.PN + ps];
-        V[0] = nd[(long)F::V1 * G.PN + ps];
+        double iT = sV[(D + 1) * QW + qw];
+        V[0] = sV[qw];
 #pragma unroll
-        for (int m = 0; m < D; ++m) V[1 + m] = nd[(long)(F::V + m) * G.PN + ps] * iT;
+        for (int m = 0; m < D; ++m) V[1 + m] = sV[(1 + m) * QW + qw] * iT;
         V[D + 1] = -iT;
       }
       w_of<D>(E, V, W[s]);
