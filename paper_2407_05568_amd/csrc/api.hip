@@ -34,6 +34,10 @@ void make_geo(const esvdw_params *p, Geo *G) {
     G->n[k] = act ? p->n[k] : 1;
     G->g[k] = act ? GH : 0;
     G->P[k] = G->n[k] + 2 * G->g[k];
+    if (k == 0) {
+      G->E0 = G->P[0];
+      G->P[0] = (G->P[0] + 15) & ~15;  // whole 128-byte lines per row
+    }
     G->lo[k] = act ? p->lo[k] : 0.0;
     G->hi[k] = act ? p->hi[k] : 1.0;
     G->dxi[k] = (G->hi[k] - G->lo[k]) / G->n[k];
@@ -77,7 +81,7 @@ const char *esvdw_strerror(int code) {
 
 void esvdw_destroy(esvdw_ctx *c) {
   if (!c) return;
-  void *bufs[] = {c->node, c->flux[0], c->flux[1], c->flux[2], c->dprod, c->met, c->stA, c->stB, c->xdot, c->xmu,
+  void *bufs[] = {c->node_mem, c->flux[0], c->flux[1], c->flux[2], c->dprod, c->met, c->stA, c->stB, c->xdot, c->xmu,
                   c->xtmp, c->omega, c->omega2, c->mterm, c->rhoG, c->scal, c->part, c->flags};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
@@ -97,7 +101,10 @@ int esvdw_create(const esvdw_params *p, esvdw_ctx **out) {
   int D = G.dim, nv = G.nv;
   c->NF = D == 1 ? NF_<1>::COUNT : (D == 2 ? NF_<2>::COUNT : NF_<3>::COUNT);
   long N = G.N;
-  bool ok = dalloc(&c->node, (size_t)c->NF * G.PN);
+  // node buffer: rows of whole cache lines, shifted so that node g0 (the first interior node)
+  // of every row starts a 128-byte line
+  bool ok = dalloc(&c->node_mem, (size_t)c->NF * G.PN + 16);
+  if (ok) c->node = c->node_mem + (16 - G.g[0]) % 16;
   for (int k = 0; k < 3; ++k) {
     c->nif[k] = 0;
     if (k < D) {

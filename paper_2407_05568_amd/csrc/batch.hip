@@ -130,9 +130,10 @@ __device__ __forceinline__ void node_chunk(const BInst &B, int inst, int x0, int
                                            const double *__restrict__ inJ, const double *__restrict__ x,
                                            const double *__restrict__ xd, const double *__restrict__ dt,
                                            unsigned *flags) {
+  // chunks run over the E0 x P1 nodes that hold data
   const int t = x0 + (int)threadIdx.x;
-  if (t < B.G.PN) {
-    const int p1 = t / B.G.P[0], p0 = t - p1 * B.G.P[0];
+  if (t < B.G.E0 * B.G.P[1]) {
+    const int p1 = t / B.G.E0, p0 = t - p1 * B.G.E0;
     const double cdt = (xd && s > 0) ? (s == 1 ? 1.0 : 0.5) * dt[inst] : 0.0;
     node_point<2>(B.G, inU + 4 * B.off, inJ + B.off, nullptr, nullptr, x + 2 * B.off, xd ? xd + 2 * B.off : nullptr,
                   cdt, nullptr, 0, B.nd, flags, p0, p1, 0);
@@ -395,18 +396,20 @@ int esvdw_batch_create(int ninst, const esvdw_params *params, esvdw_batch **out)
     B.dt_fixed = params[i].dt_fixed;
     nd_total += (long)NF_<2>::COUNT * G.PN;
     f_total += 5 * (B.nif0 + B.nif1);
-    for (long t = 0; t < G.PN; t += 256) node_items.push_back({i, (int)t, 0, 0});
+    for (long t = 0; t < (long)G.E0 * G.P[1]; t += 256) node_items.push_back({i, (int)t, 0, 0});
     B.u0 = (int)upd_items.size();
     for (long t = 0; t < G.N; t += 256) upd_items.push_back({i, (int)t, 0, 0});
     B.u1 = (int)upd_items.size();
   }
   const long total = b->off[ninst];
-  bool ok = balloc(&b->nd_pool, nd_total) && balloc(&b->f_pool, f_total) && balloc(&b->sAU, 4 * total) &&
+  bool ok = balloc(&b->nd_pool, nd_total + 16) && balloc(&b->f_pool, f_total) && balloc(&b->sAU, 4 * total) &&
             balloc(&b->sAJ, total) && balloc(&b->sBU, 4 * total) && balloc(&b->sBJ, total) &&
             balloc(&b->cpart, upd_items.size()) && balloc(&b->bar, 2) && balloc(&b->flags, 1) &&
             balloc(&b->dI, ninst) && balloc(&b->dNode, node_items.size()) && balloc(&b->dUpd, upd_items.size());
   if (ok) {
-    long nd_off = 0, f_off = 0;
+    // each instance's node buffer: PN is a multiple of 16 doubles, so starting the first at
+    // 16 - g0 puts node g0 of every row of every instance at the start of a 128-byte line
+    long nd_off = (16 - GH) % 16, f_off = 0;
     for (int i = 0; i < ninst; ++i) {
       BInst &B = b->inst[i];
       B.nd = b->nd_pool + nd_off;

@@ -16,7 +16,8 @@ struct Geo {
   int dim, nv;
   int n[3];    // interior nodes (1 in unused directions)
   int g[3];    // ghost layers of the node buffer (GH in active directions)
-  int P[3];    // padded extents of the node buffer
+  int P[3];    // node-buffer extents; P[0] is the row stride, n0 + 2 g0 rounded up to 16 doubles
+  int E0;      // nodes per node-buffer row that hold data: n0 + 2 g0
   long N, PN;  // interior / padded node counts
   double lo[3], hi[3], dxi[3], idxi[3], period[3];
   int bc[3];
@@ -364,7 +365,8 @@ struct esvdw_ctx {
   Geo G;
   int dev;
   int NF;            // node-buffer fields
-  double *node;      // NF * PN padded node data
+  double *node;      // NF * PN padded node data (rows start so that node g0 is 128-byte aligned)
+  double *node_mem;  // the allocation behind node
   double *flux[3];   // per direction: (nv + 1) * interfaces
   long nif[3];       // interfaces per direction
   double *dprod;     // 3D: 9 fields of delta_q[x_r] on a 6-ghost padded grid

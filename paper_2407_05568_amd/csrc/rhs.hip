@@ -75,7 +75,7 @@ __global__ void k_nodes(Geo G, const double *__restrict__ JU, const double *__re
                         const double *__restrict__ xn, const double *__restrict__ xd, double cdt,
                         const double *__restrict__ dp, long dpN, double *__restrict__ nd, unsigned *flags) {
   const int p0 = blockIdx.x * blockDim.x + threadIdx.x, p1 = blockIdx.y * blockDim.y + threadIdx.y, p2 = blockIdx.z;
-  if (p0 >= G.P[0] || p1 >= G.P[1]) return;
+  if (p0 >= G.E0 || p1 >= G.P[1]) return;
   node_point<D>(G, JU, J, met_in, xit_in, xn, xd, cdt, dp, dpN, nd, flags, p0, p1, p2);
 }
 
@@ -188,7 +188,7 @@ static int rhs_pipeline_d(esvdw_ctx *c, const double *JU, const double *J, const
   if (!met && D == 3)
     if (launch_dprod(c, xn, xd, cdt, st)) return -1;
   dim3 gn, bn, gu, bu;
-  node_grid(G.P[0], G.P[1], G.P[2], gn, bn);
+  node_grid(G.E0, G.P[1], G.P[2], gn, bn);
   node_grid(G.n[0], G.n[1], G.n[2], gu, bu);
   hipLaunchKernelGGL(k_nodes<D>, gn, bn, 0, st, G, JU, J, met, xit, xn, xd, cdt, c->dprod, c->dpN, c->node, c->flags);
   launch_flux_d<D>(c, 0, st);
