@@ -258,6 +258,24 @@ __device__ __forceinline__ double inv_logmean(double al, double ar, double la, d
   return (lb - la) / d;
 }
 
+// The same 1/L(al, ar) with the reciprocal of its denominator supplied, so that several
+// log means can share one division: den = logmean_den(al, ar) is the sum (near al = ar, where
+// the series in ((ar - al)/(ar + al))^2 is used) or the difference.
+__device__ __forceinline__ double logmean_den(double al, double ar) {
+  double d = ar - al, s = al + ar;
+  return fabs(d) < 0.1 * s ? s : d;
+}
+__device__ __forceinline__ double inv_logmean_r(double al, double ar, double la, double lb, double iden) {
+  double d = ar - al, s = al + ar;
+  if (fabs(d) < 0.1 * s) {
+    double f = d * iden, u = f * f;
+    double h = 1.0 + u * (1.0 / 3 + u * (1.0 / 5 + u * (1.0 / 7 + u * (1.0 / 9 + u * (1.0 / 11 + u * (1.0 / 13 +
+               u * (1.0 / 15 + u * (1.0 / 17))))))));
+    return 2.0 * h * iden;
+  }
+  return (lb - la) * iden;
+}
+
 // Multi-resolution WENO, fifth order: left limit at the right face of the centre cell of
 // (a, b, c, d, e) = w_{i-2..i+2}.  Hierarchy of central levels: 1 point (w_i), 3 points
 // (quadratic), 5 points (quartic) with linear weights wl2, wl1, wl0.
@@ -283,6 +301,30 @@ __device__ __forceinline__ double mrweno5(const Geo &G, double a, double b, doub
   double w1 = G.wl2 * (e5 * e3) * (e1 + tau);
   double top = (q5 - G.wl1 * q3 - G.wl2 * c) * G.iwl0;
   return (w5 * top + w3 * q3 + w1 * c) / (w5 + w3 + w1);
+}
+
+// mrweno5 as a fraction num / den with den > 0 (the caller divides, possibly sharing the division)
+__device__ __forceinline__ void mrweno5_frac(const Geo &G, double a, double b, double c, double d, double e, double &num,
+                                             double &den) {
+  double q5 = (2.0 * a - 13.0 * b + 47.0 * c + 27.0 * d - 3.0 * e) * (1.0 / 60.0);
+  double q3 = (-b + 5.0 * c + 2.0 * d) * (1.0 / 6.0);
+  double dl = c - b, dr = d - c;
+  double s1 = fmin(dl * dl, dr * dr);
+  double t1 = b - 2.0 * c + d, t2 = d - b;
+  double s3 = (13.0 / 12.0) * t1 * t1 + 0.25 * t2 * t2;
+  double s5 = (c * (231153.0 * c - 299076.0 * (b + d) + 67923.0 * (a + e)) + 104963.0 * (b * b + d * d) -
+               51001.0 * (a * b + d * e) + 179098.0 * b * d - 38947.0 * (b * e + a * d) + 6908.0 * (a * a + e * e) +
+               8209.0 * a * e) *
+              (1.0 / 5040.0);
+  double tt = 0.5 * (fabs(s5 - s1) + fabs(s5 - s3));
+  double tau = tt * tt;
+  double e5 = s5 + G.weps, e3 = s3 + G.weps, e1 = s1 + G.weps;
+  double w5 = G.wl0 * (e3 * e1) * (e5 + tau);
+  double w3 = G.wl1 * (e5 * e1) * (e3 + tau);
+  double w1 = G.wl2 * (e5 * e3) * (e1 + tau);
+  double top = (q5 - G.wl1 * q3 - G.wl2 * c) * G.iwl0;
+  num = w5 * top + w3 * q3 + w1 * c;
+  den = w5 + w3 + w1;
 }
 
 // ---------------------------------------------------------------------------------

@@ -181,19 +181,23 @@ __device__ __forceinline__ void ec_pair(const Geo &G, const Pq<D> &l, const Pq<D
   double rTm = 0.5 * (l.rho * l.iT + r.rho * r.iT), gm = 0.5 * (l.g + r.g);
   double rum = 0.5 * (l.rho * ul + r.rho * ur), um = 0.5 * (ul + ur);
   double Rb_Pi = G.R * G.b * l.iob * r.iob;
-  double iTmean = 2.0 / (l.T + r.T);
-  double Dd = G.R * inv_logmean(l.rho, r.rho, l.lr, r.lr) + Rb_Pi - 2.0 * G.a * iTmean;
-  if (G.b > 0.0) {
-    double obl = 1.0 - G.b * l.rho, obr = 1.0 - G.b * r.rho;
-    Dd += G.R * G.b * inv_logmean(obl, obr, l.lb, r.lb);
-  }
+  // the denominators of 1/L(rho), 1/L(1 - b rho), 1/L(T) and of the mean 1/{T} share one division
+  const double obl = 1.0 - G.b * l.rho, obr = 1.0 - G.b * r.rho;
+  const double dR = logmean_den(l.rho, r.rho), dB = logmean_den(obl, obr), dT = logmean_den(l.T, r.T);
+  const double sT = l.T + r.T;
+  const double t1 = dR * dB, t2 = dT * sT, rq = 1.0 / (t1 * t2), r1 = rq * t2, r2 = rq * t1;
+  double iTmean = 2.0 * (r2 * dT);
+  double Dd = G.R * inv_logmean_r(l.rho, r.rho, l.lr, r.lr, r1 * dB) + Rb_Pi - 2.0 * G.a * iTmean;
+  if (G.b > 0.0) Dd += G.R * G.b * inv_logmean_r(obl, obr, l.lb, r.lb, r1 * dR);
   double A = Rb_Pi - G.a * iTmean;
   double v2T = 0.0;
 #pragma unroll
   for (int m = 0; m < D; ++m) v2T += l.v[m] * l.v[m] * l.iT + r.v[m] * r.v[m] * r.iT;
-  double Kk = 0.25 * v2T - G.cv * Tm * inv_logmean(l.T, r.T, l.lt, r.lt) + 2.0 * G.a * rTm;
+  double Kk = 0.25 * v2T - G.cv * Tm * inv_logmean_r(l.T, r.T, l.lt, r.lt, r2 * sT) + 2.0 * G.a * rTm;
   if (!(Dd > 0.0)) bad = 1u;
-  double Fr = (rum * A + gm * um) / Dd;
+  // and the two final divisions (by D and by {1/T}) share another
+  const double rd = 1.0 / (Dd * iTm);
+  double Fr = (rum * A + gm * um) * (rd * iTm);
   double pt = rhom * Tm * gm;
   double sum = 0.0;
 #pragma unroll
@@ -203,7 +207,7 @@ __device__ __forceinline__ void ec_pair(const Geo &G, const Pq<D> &l, const Pq<D
     sum += 0.5 * (l.v[m] * l.iT + r.v[m] * r.iT) * Fv;
   }
   out[0] = Fr;
-  out[D + 1] = (sum - Kk * Fr + G.a * rum * rTm) / iTm;
+  out[D + 1] = (sum - Kk * Fr + G.a * rum * rTm) * (rd * Dd);
   out[D + 2] = mbt;
 }
 
@@ -350,22 +354,19 @@ __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict
   if (G.diss) {
     const long pc = ((long)(i2 + G.g[2]) * G.P[1] + (i1 + G.g[1])) * G.P[0] + (i0 + G.g[0]);
     const long pr = pc + sK;
+    // (the divisions of the averaged state are grouped so that each group shares one)
     double rl = nd[F::RHO * G.PN + pc], rr = nd[F::RHO * G.PN + pr];
     double pl = nd[F::P * G.PN + pc], pq = nd[F::P * G.PN + pr];
-    double ilr = inv_logmean(rl, rr, nd[F::LNR * G.PN + pc], nd[F::LNR * G.PN + pr]);
-    // rho/p and its logarithm
-    double zl = rl / pl, zr = rr / pq;
-    double ilz = inv_logmean(zl, zr, nd[F::LNR * G.PN + pc] - nd[F::LNP * G.PN + pc],
-                             nd[F::LNR * G.PN + pr] - nd[F::LNP * G.PN + pr]);
-    double rb = 1.0 / ilr;     // L(rho)
-    double pb = rb * ilz;      // L(rho)/L(rho/p)
+    // rho/p at the two nodes and its logarithm
+    const double rpp = 1.0 / (pl * pq);
+    double zl = rl * (pq * rpp), zr = rr * (pl * rpp);
+    const double dR = logmean_den(rl, rr), dZ = logmean_den(zl, zr), rRZ = 1.0 / (dR * dZ);
+    double ilr = inv_logmean_r(rl, rr, nd[F::LNR * G.PN + pc], nd[F::LNR * G.PN + pr], rRZ * dZ);
+    double ilz = inv_logmean_r(zl, zr, nd[F::LNR * G.PN + pc] - nd[F::LNP * G.PN + pc],
+                               nd[F::LNR * G.PN + pr] - nd[F::LNP * G.PN + pr], rRZ * dR);
     double vb[D];
 #pragma unroll
     for (int m = 0; m < D; ++m) vb[m] = 0.5 * (nd[(long)(F::V + m) * G.PN + pc] + nd[(long)(F::V + m) * G.PN + pr]);
-    double ob = 1.0 - G.b * rb;
-    double Tb = (pb + G.a * rb * rb) * ob * ilr * G.iR;
-    double iob = 1.0 / ob;
-    double c2 = (1.0 + G.delta) * G.R * Tb * iob * iob - 2.0 * G.a * rb;
     double mm[D], L2 = 0.0;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -374,7 +375,22 @@ __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict
     }
     double mtb = 0.5 * (nd[(long)(F::XS + K) * G.PN + pc] + nd[(long)(F::XS + K) * G.PN + pr]);
     double L = sqrt(L2);
-    double iL = 1.0 / L;
+    // L(rho) = 1/ilr and 1/L share a division
+    const double rLL = 1.0 / (ilr * L);
+    double rb = rLL * L;       // L(rho)
+    double iL = rLL * ilr;
+    double pb = rb * ilz;      // L(rho)/L(rho/p)
+    double ob = 1.0 - G.b * rb;
+    double Tb = (pb + G.a * rb * rb) * ob * ilr * G.iR;
+    // c^2 (1 - b rho)^2 and the S_2 factor R T - 2 a rho (1 - b rho)^2; 1/(1 - b rho), 1/c^2 and
+    // 1/(c_v ac) share a division
+    double c2o = (1.0 + G.delta) * G.R * Tb - 2.0 * G.a * rb * ob * ob;
+    double ac = G.R * Tb - 2.0 * G.a * rb * ob * ob;
+    const double rD = 1.0 / (ob * c2o * ac);
+    double iob = rD * (c2o * ac);
+    double c2 = c2o * iob * iob;
+    double ic2 = ob * ob * (rD * (ob * ac));
+    double iac = rD * (ob * c2o);
     Eig<D> E;
 #pragma unroll
     for (int j = 0; j < D; ++j) E.n[j] = mm[j] * iL;
@@ -414,9 +430,7 @@ __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict
     E.H = (Eb + pb) * ilr;
     E.c = sqrt(c2);
     E.c2G = c2 * G.cv * ob * G.iR;  // c^2 / Gamma with Gamma = R/(c_v (1 - b rho))
-    double ac = G.R * Tb - 2.0 * G.a * rb * ob * ob;
-    double ic2 = 1.0 / c2;
-    double S0 = 0.5 * rb * Tb * ic2, S1 = G.R * G.R * rb * Tb * Tb * ic2 / (G.cv * ac), St = rb * Tb;
+    double S0 = 0.5 * rb * Tb * ic2, S1 = G.R * G.R * rb * Tb * Tb * ic2 * (iac * G.delta * G.iR), St = rb * Tb;
     if (!(S0 > 0.0) || !(S1 > 0.0)) bad = 1u;
     E.s0 = sqrt(fabs(S0));
     E.s1 = sqrt(fabs(S1));
@@ -449,12 +463,14 @@ __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict
     double y[NV];
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
-      double wm = mrweno5(G, W[0][c], W[1][c], W[2][c], W[3][c], W[4][c]);
-      double wp = mrweno5(G, W[5][c], W[4][c], W[3][c], W[2][c], W[1][c]);
-      double jr = wp - wm, j0 = W[3][c] - W[2][c];
+      // [W]^WENO = wp - wm = (np dm - nm dp) / (dp dm), dp, dm > 0: one division per component
+      double nm, dm, np, dp;
+      mrweno5_frac(G, W[0][c], W[1][c], W[2][c], W[3][c], W[4][c], nm, dm);
+      mrweno5_frac(G, W[5][c], W[4][c], W[3][c], W[2][c], W[1][c], np, dp);
+      double jn = np * dm - nm * dp, j0 = W[3][c] - W[2][c];
       // a plain jump below the rounding scale of W (2^-40 of its terms) counts as zero
       if (fabs(j0) <= ldexp(As[c], -40)) j0 = 0.0;
-      y[c] = ((jr > 0.0 && j0 > 0.0) || (jr < 0.0 && j0 < 0.0)) ? jr : 0.0;
+      y[c] = ((jn > 0.0 && j0 > 0.0) || (jn < 0.0 && j0 < 0.0)) ? jn / (dp * dm) : 0.0;
     }
     // R y in the rotated frame, then rotate the momentum back (T^T)
     double b0 = E.s0 * y[0], b1 = E.s1 * y[1], b2 = E.s0 * y[D + 1];
