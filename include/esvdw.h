@@ -227,6 +227,15 @@ int esvdw_batch_init_state(esvdw_batch *b, const double *prim, const double *J, 
 int esvdw_batch_stage(esvdw_batch *b, int s, const double *JU0, const double *J0, const double *JUs,
                       const double *Js, double *JUout, double *Jout, double *x, const double *xdot, double *dt,
                       hipStream_t stream);
+/* Mesh redistribution of every instance (Section 4), as redistribute_mesh with a fixed sweep
+ * count: monitor omega from (JU, J) with each instance's monitor parameters and per-instance
+ * maxima, n_filter low-pass passes, mu Jacobi sweeps from x^[0] = x, the movement limiter (one
+ * Delta_gamma per instance), the CFL step dt[i] (as in esvdw_batch_stage) and
+ * xdot = Delta_gamma (x^[mu] - x)/dt (pool of 2 fields).  x is not modified.  Requires that all
+ * instances use fixed_mu = 1 and share n_filter and mu (ESVDW_EINVAL otherwise).  A moving-mesh
+ * step is esvdw_batch_redistribute followed by esvdw_batch_step with this xdot. */
+int esvdw_batch_redistribute(esvdw_batch *b, const double *JU, const double *J, const double *x, double *xdot,
+                             double *dt, hipStream_t stream);
 /* One full SSP-RK3 step of every instance in place (three esvdw_batch_stage launches through
  * the batch's own stage buffers); capturable in a HIP graph. */
 int esvdw_batch_step(esvdw_batch *b, double *JU, double *J, double *x, const double *xdot, double *dt,

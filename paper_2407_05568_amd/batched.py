@@ -10,7 +10,9 @@ initial state, HIP events on the launch stream) and keeps the fastest; the varia
 identical results, so the choice only moves speed.
 
 Run as a module for the 256-instance batch (prints one JSON line, progress on stderr):
-    python -m paper_2407_05568_amd.batched --count 256 --steps 10
+    python -m paper_2407_05568_amd.batched --count 256 --steps 10 [--moving]
+With --moving a step is the mesh redistribution of every instance (monitor, 5 filter passes,
+10 Jacobi sweeps, limiter, CFL) followed by the three RK stages on the moving meshes.
 """
 import argparse
 import json
@@ -40,6 +42,8 @@ class BatchRun:
         self.J = torch.zeros(tot, **f64)
         self.JU = torch.zeros(4 * tot, **f64)
         self.dt = torch.zeros(len(problems), **f64)
+        self.xdot = torch.zeros(2 * tot, **f64)
+        self.moving = False
         pool = np.zeros(4 * tot)
         for i, pr in enumerate(prims):
             pool[4 * self.off[i]:4 * self.off[i + 1]] = np.asarray(pr, dtype=np.float64).reshape(-1)
@@ -53,8 +57,13 @@ class BatchRun:
         self.J.copy_(self.J0)
         self.x.copy_(self.x0)
 
-    def step(self, xdot=None, stream=None):
-        self.B.step(self.JU, self.J, self.x, xdot, self.dt, stream or self.stream)
+    def step(self, stream=None):
+        st = stream or self.stream
+        if self.moving:
+            self.B.redistribute(self.JU, self.J, self.x, self.xdot, self.dt, st)
+            self.B.step(self.JU, self.J, self.x, self.xdot, self.dt, st)
+        else:
+            self.B.step(self.JU, self.J, self.x, None, self.dt, st)
 
     def time_steps(self, steps):
         torch = self.torch
@@ -83,9 +92,11 @@ def autotune(run, steps=2):
     return best, times
 
 
-def launches_per_step(B, v):
-    """Kernel launches of one step: 3 for the persistent kernel, 2 + 3 x 3 for the phased ones."""
-    return 3 if v < B.variants() // 2 else 11
+def launches_per_step(B, v, moving=False, n_filter=5, mu=10):
+    """Kernel launches of one step: 3 for the persistent kernel, 2 + 3 x 3 for the phased ones,
+    plus 9 + n_filter + mu for the redistribution of a moving step."""
+    n = 3 if v < B.variants() // 2 else 11
+    return n + (9 + n_filter + mu if moving else 0)
 
 
 def batch_problems(seed, count):
@@ -100,11 +111,13 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--moving", action="store_true")
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available(), "the batched run needs a GPU"
     problems, prims = batch_problems(args.seed, args.count)
     run = BatchRun(torch, problems, prims)
+    run.moving = args.moving
     nodes = run.B.total
     _log("batch: %d instances, %d nodes" % (args.count, nodes))
     best, times = (0, {}) if args.no_tune else autotune(run)
@@ -129,10 +142,12 @@ def main():
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
     flags = run.B.status()
-    out = {"metric": "FP64 node-stage updates/s, batched independent 2D problems", "value": 3 * nodes / (ms / 1e3),
+    out = {"metric": "FP64 node-stage updates/s, batched independent 2D problems%s" % (
+               " (moving meshes)" if args.moving else ""), "value": 3 * nodes / (ms / 1e3),
            "unit": "node-stages/s", "ms_per_step": ms, "steps": args.steps, "instances": args.count, "nodes": nodes,
            "variant": best, "mode": "persistent" if best < run.B.variants() // 2 else "phased",
-           "variant_ms": times, "launches_per_step": launches_per_step(run.B, best), "status_flags": flags}
+           "variant_ms": times, "launches_per_step": launches_per_step(run.B, best, args.moving), "moving": args.moving,
+           "status_flags": flags}
     print(json.dumps(out), flush=True)
 
 

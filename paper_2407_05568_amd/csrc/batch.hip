@@ -5,11 +5,13 @@
 //   node data of every padded node of every instance
 //   interface fluxes of every instance, both directions
 //   flux differences and the RK combination (+ x^{n+1} = x^n + dt xdot at stage 2)
-// The work items of a phase (interface tiles, or chunks of 256 nodes) are listed instance by
-// instance.  Workgroups are handed
-// to the 8 XCDs round-robin, so the blocks with equal blockIdx % 8 share one XCD; each such
-// group walks one contiguous eighth of the list, and neighbouring tiles (which read the same
-// node data) share that XCD's L2.
+// The same phases also run as separate launches (the phased kernels), and the mesh
+// redistribution of Section 4 (monitor with per-instance maxima, filter, Jacobi, limiter,
+// mesh velocity) runs batched over the same work lists.  The work items of a phase
+// (interface tiles, or chunks of 256 nodes) are listed instance by instance.  Workgroups are
+// handed to the 8 XCDs round-robin, so the blocks with equal blockIdx % 8 share one XCD; each
+// such group walks one contiguous eighth of the list, and neighbouring tiles (which read the
+// same node data) share that XCD's L2.
 #include <stdlib.h>
 #include <string.h>
 
@@ -17,6 +19,7 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "meshdev.h"
 #include "scheme.h"
 
 #define HIPOK(x) ((x) == hipSuccess)
@@ -29,6 +32,8 @@ struct BInst {
   long nif0, nif1;
   double cfl, dt_fixed;
   int u0, u1;       // the instance's chunks in the update list
+  int mkind, kappa, var0, var1, nterm;  // monitor of the mesh redistribution
+  double alpha[3];
 };
 
 // a work item: a flux tile (first interface (x0, y0), direction k) or a chunk of 256
@@ -62,6 +67,9 @@ struct esvdw_batch {
   int nNode, nFlux, nUpd;
   double *nd_pool, *f_pool, *sAU, *sAJ, *sBU, *sBJ, *cpart;
   unsigned *bar, *flags;
+  // mesh redistribution (fixed sweep count, shared by all instances)
+  int redist_ok, n_filter, mu;
+  double *rg, *term, *omA, *omB, *xa, *xb, *part3, *monmax, *gam;
 };
 
 // ---- grid-wide barrier with a bounded wait ---------------------------------------------------
@@ -261,6 +269,139 @@ __global__ void __launch_bounds__(256) k_bph_update(const BInst *__restrict__ I,
   update_chunk(I[w.inst], w.inst, w.x0, s, bU, bJ, inU, inJ, outU, outJ, x, xd, dt, flags);
 }
 
+// ---- batched mesh redistribution (Section 4): the same per-node building blocks over the
+// update list's 256-node chunks; per-instance maxima / minima through chunk partials ----------
+
+// interior node (i0, i1) of this thread in a chunk; false past the instance's last node
+__device__ __forceinline__ bool chunk_node(const BInst &B, int x0, int &i0, int &i1, long &t) {
+  const int tt = x0 + (int)threadIdx.x;
+  if (tt >= B.G.N) return false;
+  i1 = tt / B.G.n[0];
+  i0 = tt - i1 * B.G.n[0];
+  t = tt;
+  return true;
+}
+
+__global__ void __launch_bounds__(256) k_bm_rhoG(const BInst *__restrict__ I, const BItem *__restrict__ iupd, int nupd,
+                                                 const double *__restrict__ JU, const double *__restrict__ J,
+                                                 double *rg) {
+  const int it = xcd_item(nupd);
+  if (it < 0) return;
+  const BItem w = iupd[it];
+  const BInst &B = I[w.inst];
+  int i0, i1;
+  long t;
+  if (chunk_node(B, w.x0, i0, i1, t)) rhoG_point<2>(B.G, JU + 4 * B.off, J + B.off, rg + 2 * B.off, t);
+}
+
+__global__ void __launch_bounds__(256) k_bm_terms(const BInst *__restrict__ I, const BItem *__restrict__ iupd, int nupd,
+                                                  const double *__restrict__ rg, double *term, double *part3) {
+  const int it = xcd_item(nupd);
+  if (it < 0) return;
+  const BItem w = iupd[it];
+  const BInst &B = I[w.inst];
+  int i0, i1;
+  long t;
+  double val[3] = {0.0, 0.0, 0.0};
+  if (chunk_node(B, w.x0, i0, i1, t))
+    mon_terms_point<2>(B.G, B.mkind, B.kappa, B.var0, B.var1, rg + 2 * B.off, term + 3 * B.off, i0, i1, 0, val);
+  for (int q = 0; q < 3; ++q) {
+    double m = block_max(val[q]);
+    if (threadIdx.x == 0) part3[(long)q * nupd + it] = m;
+  }
+}
+
+// per-instance reductions of chunk partials: maxima of the 3 monitor terms, or the limiter minimum
+__global__ void __launch_bounds__(256) k_bm_max3(const BInst *__restrict__ I, const double *__restrict__ part3,
+                                                 int nupd, double *monmax) {
+  const BInst &B = I[blockIdx.x];
+  for (int q = 0; q < 3; ++q) {
+    double m = 0.0;
+    for (int u = B.u0 + (int)threadIdx.x; u < B.u1; u += 256) m = fmax(m, part3[(long)q * nupd + u]);
+    m = block_max(m);
+    if (threadIdx.x == 0) monmax[3 * blockIdx.x + q] = m;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_bm_min(const BInst *__restrict__ I, const double *__restrict__ part,
+                                                double *gam) {
+  const BInst &B = I[blockIdx.x];
+  double m = 1.0;
+  for (int u = B.u0 + (int)threadIdx.x; u < B.u1; u += 256) m = fmin(m, part[u]);
+  m = block_min(m);
+  if (threadIdx.x == 0) gam[blockIdx.x] = m;
+}
+
+__global__ void __launch_bounds__(256) k_bm_omega(const BInst *__restrict__ I, const BItem *__restrict__ iupd, int nupd,
+                                                  const double *__restrict__ term, const double *__restrict__ monmax,
+                                                  double *om) {
+  const int it = xcd_item(nupd);
+  if (it < 0) return;
+  const BItem w = iupd[it];
+  const BInst &B = I[w.inst];
+  int i0, i1;
+  long t;
+  if (chunk_node(B, w.x0, i0, i1, t))
+    om[B.off + t] = mon_omega_point(B.G, B.nterm, B.alpha, term + 3 * B.off, monmax + 3 * w.inst, t);
+}
+
+__global__ void __launch_bounds__(256) k_bm_filter(const BInst *__restrict__ I, const BItem *__restrict__ iupd,
+                                                   int nupd, const double *__restrict__ in, double *out) {
+  const int it = xcd_item(nupd);
+  if (it < 0) return;
+  const BItem w = iupd[it];
+  const BInst &B = I[w.inst];
+  int i0, i1;
+  long t;
+  if (chunk_node(B, w.x0, i0, i1, t)) out[B.off + t] = filter_point<2>(B.G, in + B.off, i0, i1, 0);
+}
+
+__global__ void __launch_bounds__(256) k_bm_jacobi(const BInst *__restrict__ I, const BItem *__restrict__ iupd,
+                                                   int nupd, const double *__restrict__ om,
+                                                   const double *__restrict__ xin, double *xout) {
+  const int it = xcd_item(nupd);
+  if (it < 0) return;
+  const BItem w = iupd[it];
+  const BInst &B = I[w.inst];
+  int i0, i1;
+  long t;
+  if (chunk_node(B, w.x0, i0, i1, t)) jacobi_point<2>(B.G, om + B.off, xin + 2 * B.off, xout + 2 * B.off, i0, i1, 0);
+}
+
+__global__ void __launch_bounds__(256) k_bm_limiter(const BInst *__restrict__ I, const BItem *__restrict__ iupd,
+                                                    int nupd, const double *__restrict__ xn,
+                                                    const double *__restrict__ xmu, double *part) {
+  const int it = xcd_item(nupd);
+  if (it < 0) return;
+  const BItem w = iupd[it];
+  const BInst &B = I[w.inst];
+  int i0, i1;
+  long t;
+  double g = 1.0;
+  if (chunk_node(B, w.x0, i0, i1, t)) g = limiter_point<2>(B.G, xn + 2 * B.off, xmu + 2 * B.off, i0, i1, 0);
+  g = block_min(g);
+  if (threadIdx.x == 0) part[it] = g;
+}
+
+// xdot = Delta_gamma (x^[mu] - x^n) / dt per instance
+__global__ void __launch_bounds__(256) k_bm_xdot(const BInst *__restrict__ I, const BItem *__restrict__ iupd, int nupd,
+                                                 const double *__restrict__ xn, const double *__restrict__ xmu,
+                                                 const double *__restrict__ gam, const double *__restrict__ dt,
+                                                 double *xdot) {
+  const int it = xcd_item(nupd);
+  if (it < 0) return;
+  const BItem w = iupd[it];
+  const BInst &B = I[w.inst];
+  int i0, i1;
+  long t;
+  if (!chunk_node(B, w.x0, i0, i1, t)) return;
+  const double g = gam[w.inst], d = dt[w.inst];
+  for (int j = 0; j < 2; ++j) {
+    const long q = 2 * B.off + (long)j * B.G.N + t;
+    xdot[q] = g * (xmu[q] - xn[q]) / d;
+  }
+}
+
 // ---- host side ---------------------------------------------------------------------------------
 
 template <int V> static int stage_blocks(int ncu) {
@@ -361,8 +502,9 @@ extern "C" {
 
 void esvdw_batch_destroy(esvdw_batch *b) {
   if (!b) return;
-  void *bufs[] = {b->dI,  b->dNode, b->dFlux, b->dUpd, b->nd_pool, b->f_pool, b->sAU,
-                  b->sAJ, b->sBU,   b->sBJ,   b->cpart, b->bar,    b->flags};
+  void *bufs[] = {b->dI,  b->dNode, b->dFlux, b->dUpd, b->nd_pool, b->f_pool, b->sAU,  b->sAJ,
+                  b->sBU, b->sBJ,   b->cpart, b->bar,  b->flags,   b->rg,     b->term, b->omA,
+                  b->omB, b->xa,    b->xb,    b->part3, b->monmax, b->gam};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   delete b;
@@ -394,6 +536,12 @@ int esvdw_batch_create(int ninst, const esvdw_params *params, esvdw_batch **out)
     B.nif1 = (long)G.n[0] * (G.n[1] + 1);
     B.cfl = params[i].cfl;
     B.dt_fixed = params[i].dt_fixed;
+    B.mkind = params[i].monitor_kind;
+    B.kappa = params[i].kappa;
+    B.var0 = params[i].mon_var[0];
+    B.var1 = params[i].mon_var[1];
+    B.nterm = B.mkind == ESVDW_MON_VDW ? B.kappa + 1 : 2;
+    for (int q = 0; q < 3; ++q) B.alpha[q] = params[i].alpha[q];
     nd_total += (long)NF_<2>::COUNT * G.PN;
     f_total += 5 * (B.nif0 + B.nif1);
     for (long t = 0; t < (long)G.E0 * G.P[1]; t += 256) node_items.push_back({i, (int)t, 0, 0});
@@ -405,7 +553,18 @@ int esvdw_batch_create(int ninst, const esvdw_params *params, esvdw_batch **out)
   bool ok = balloc(&b->nd_pool, nd_total + 16) && balloc(&b->f_pool, f_total) && balloc(&b->sAU, 4 * total) &&
             balloc(&b->sAJ, total) && balloc(&b->sBU, 4 * total) && balloc(&b->sBJ, total) &&
             balloc(&b->cpart, upd_items.size()) && balloc(&b->bar, 2) && balloc(&b->flags, 1) &&
-            balloc(&b->dI, ninst) && balloc(&b->dNode, node_items.size()) && balloc(&b->dUpd, upd_items.size());
+            balloc(&b->dI, ninst) && balloc(&b->dNode, node_items.size()) && balloc(&b->dUpd, upd_items.size()) &&
+            balloc(&b->rg, 2 * total) && balloc(&b->term, 3 * total) && balloc(&b->omA, total) &&
+            balloc(&b->omB, total) && balloc(&b->xa, 2 * total) && balloc(&b->xb, 2 * total) &&
+            balloc(&b->part3, 3 * upd_items.size()) && balloc(&b->monmax, 3 * (size_t)ninst) &&
+            balloc(&b->gam, ninst);
+  // the batched redistribution runs a fixed number of filter passes and Jacobi sweeps for all
+  // instances: it is available when they agree on both
+  b->n_filter = params[0].n_filter;
+  b->mu = params[0].mu;
+  b->redist_ok = 1;
+  for (int i = 0; i < ninst; ++i)
+    if (params[i].n_filter != b->n_filter || params[i].mu != b->mu || !params[i].fixed_mu) b->redist_ok = 0;
   if (ok) {
     // each instance's node buffer: PN is a multiple of 16 doubles, so starting the first at
     // 16 - g0 puts node g0 of every row of every instance at the start of a 128-byte line
@@ -498,6 +657,39 @@ int esvdw_batch_stage(esvdw_batch *b, int s, const double *JU0, const double *J0
   if (!b || s < 0 || s > 2 || !JU0 || !J0 || !JUs || !Js || !JUout || !Jout || !x || !dt) return ESVDW_EINVAL;
   if (JUout == JUs || Jout == Js) return ESVDW_EINVAL;
   return launch_stage(b, s, JU0, J0, JUs, Js, JUout, Jout, x, xdot, dt, st) ? ESVDW_EHIP : ESVDW_OK;
+}
+
+int esvdw_batch_redistribute(esvdw_batch *b, const double *JU, const double *J, const double *x, double *xdot,
+                             double *dt, hipStream_t st) {
+  if (!b || !JU || !J || !x || !xdot || !dt) return ESVDW_EINVAL;
+  if (!b->redist_ok) return ESVDW_EINVAL;
+  const unsigned gu = xcd_grid(b->nUpd);
+  const int ni = b->ninst, nu = b->nUpd;
+  hipLaunchKernelGGL(k_bm_rhoG, dim3(gu), dim3(256), 0, st, b->dI, b->dUpd, nu, JU, J, b->rg);
+  hipLaunchKernelGGL(k_bm_terms, dim3(gu), dim3(256), 0, st, b->dI, b->dUpd, nu, b->rg, b->term, b->part3);
+  hipLaunchKernelGGL(k_bm_max3, dim3(ni), dim3(256), 0, st, b->dI, b->part3, nu, b->monmax);
+  double *cur = b->omA, *oth = b->omB;
+  hipLaunchKernelGGL(k_bm_omega, dim3(gu), dim3(256), 0, st, b->dI, b->dUpd, nu, b->term, b->monmax, cur);
+  for (int i = 0; i < b->n_filter; ++i) {
+    hipLaunchKernelGGL(k_bm_filter, dim3(gu), dim3(256), 0, st, b->dI, b->dUpd, nu, cur, oth);
+    double *tmp = cur;
+    cur = oth;
+    oth = tmp;
+  }
+  // Jacobi from x^[0] = x^n, ping-pong between the batch's two mesh buffers
+  const double *xin = x;
+  double *xo = b->xa;
+  for (int k = 0; k < b->mu; ++k) {
+    hipLaunchKernelGGL(k_bm_jacobi, dim3(gu), dim3(256), 0, st, b->dI, b->dUpd, nu, cur, xin, xo);
+    xin = xo;
+    xo = xo == b->xa ? b->xb : b->xa;
+  }
+  hipLaunchKernelGGL(k_bm_limiter, dim3(gu), dim3(256), 0, st, b->dI, b->dUpd, nu, x, xin, b->part3);
+  hipLaunchKernelGGL(k_bm_min, dim3(ni), dim3(256), 0, st, b->dI, b->part3, b->gam);
+  hipLaunchKernelGGL(k_bph_cfl, dim3(gu), dim3(256), 0, st, b->dI, b->dUpd, nu, JU, J, x, b->cpart);
+  hipLaunchKernelGGL(k_bph_dt, dim3(ni), dim3(256), 0, st, b->dI, b->cpart, dt);
+  hipLaunchKernelGGL(k_bm_xdot, dim3(gu), dim3(256), 0, st, b->dI, b->dUpd, nu, x, xin, b->gam, dt, xdot);
+  return hipGetLastError() == hipSuccess ? ESVDW_OK : ESVDW_EHIP;
 }
 
 int esvdw_batch_step(esvdw_batch *b, double *JU, double *J, double *x, const double *xdot, double *dt,

@@ -1,9 +1,10 @@
 // mesh.hip -- adaptive moving mesh (Section 4): monitor, low-pass filter, Jacobi sweeps
 // of the discretised Winslow equations, movement limiter, CFL time step (eq. cfl) and the
-// mesh velocity.  All global reductions are wavefront shuffles + one atomic per block on a
-// device scalar of the context.
+// mesh velocity.  Global reductions: per-block partials (wavefront shuffles, then LDS), reduced
+// by a one-block kernel into a device scalar of the context.
 #include "common.h"
 #include "kernels.h"
+#include "meshdev.h"
 #include "scheme.h"
 
 static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -48,16 +49,7 @@ template <int D>
 __global__ void k_rho_G(Geo G, const double *__restrict__ JU, const double *__restrict__ J, double *__restrict__ rg) {
   NODE_COORDS(G.n[0], G.n[1]);
   if (!inside) return;
-  const long t = lin(G, i0, i1, i2);
-  double iJ = 1.0 / J[t];
-  double rho = JU[t] * iJ, v2 = 0.0;
-  for (int m = 0; m < D; ++m) {
-    double v = JU[(long)(1 + m) * G.N + t] * iJ / rho;
-    v2 += v * v;
-  }
-  double T = eos_T_rho_e(G, rho, JU[(long)(D + 1) * G.N + t] * iJ / rho - 0.5 * v2);
-  rg[t] = rho;
-  rg[G.N + t] = eos_G(G, rho, T);
+  rhoG_point<D>(G, JU, J, rg, lin(G, i0, i1, i2));
 }
 
 // term t of the monitor at each node; maxima into scal[SC_MON + t]
@@ -65,38 +57,9 @@ template <int D>
 __global__ void k_mon_terms(Geo G, int kind, int kappa, int var0, int var1, const double *__restrict__ rg,
                             double *__restrict__ term, double *part, long npart) {
   NODE_COORDS(G.n[0], G.n[1]);
-  const long t = inside ? lin(G, i0, i1, i2) : 0;
-  int nterm = kind == ESVDW_MON_VDW ? kappa + 1 : 2;
   double val[3] = {0.0, 0.0, 0.0};
-  if (inside) {
-    for (int q = 0; q < nterm; ++q) {
-      const double *f;
-      bool second;
-      if (kind == ESVDW_MON_VDW) {
-        if (q < kappa) {
-          f = ((q == 0 ? var0 : var1) == ESVDW_VAR_G) ? rg + G.N : rg;
-          second = false;
-        } else {
-          f = rg + G.N;
-          second = true;
-        }
-      } else {
-        f = rg;
-        second = q == 1;
-      }
-      double f0 = f[t], s2 = 0.0;
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        int e0 = k == 0, e1 = k == 1, e2 = k == 2;
-        double fp = f[state_index(G, i0 + e0, i1 + e1, i2 + e2)];
-        double fm = f[state_index(G, i0 - e0, i1 - e1, i2 - e2)];
-        double g = second ? (fp - 2.0 * f0 + fm) * G.idxi[k] * G.idxi[k] : (fp - fm) * 0.5 * G.idxi[k];
-        s2 += g * g;
-      }
-      val[q] = kind == ESVDW_MON_VDW ? s2 : sqrt(s2);
-      term[(long)q * G.N + t] = val[q];
-    }
-  }
+  int nterm = kind == ESVDW_MON_VDW ? kappa + 1 : 2;
+  if (inside) mon_terms_point<D>(G, kind, kappa, var0, var1, rg, term, i0, i1, i2, val);
   for (int q = 0; q < 3; ++q) {
     if (q >= nterm) break;
     double mq = block_max(val[q]);
@@ -109,13 +72,8 @@ __global__ void k_mon_omega(Geo G, int nterm, double a0, double a1, double a2, c
   NODE_COORDS(G.n[0], G.n[1]);
   if (!inside) return;
   const long t = lin(G, i0, i1, i2);
-  double al[3] = {a0, a1, a2};
-  double s = 1.0;
-  for (int q = 0; q < nterm; ++q) {
-    double m = scal[SC_MON + q];
-    if (m > 0.0) s += al[q] * term[(long)q * G.N + t] / m;
-  }
-  omega[t] = sqrt(s);
+  const double al[3] = {a0, a1, a2};
+  omega[t] = mon_omega_point(G, nterm, al, term, scal + SC_MON, t);
 }
 
 // omega <- sum_{j in {-1,0,1}^d} 2^-(|j|_1 + d) omega_{i+j}; replicate / wrap at the boundary
@@ -123,17 +81,7 @@ template <int D>
 __global__ void k_filter(Geo G, const double *__restrict__ in, double *__restrict__ out) {
   NODE_COORDS(G.n[0], G.n[1]);
   if (!inside) return;
-  const long t = lin(G, i0, i1, i2);
-  double s = 0.0;
-  const int r1 = D > 1, r2 = D > 2;
-  for (int j2 = -r2; j2 <= r2; ++j2)
-    for (int j1 = -r1; j1 <= r1; ++j1)
-#pragma unroll
-      for (int j0 = -1; j0 <= 1; ++j0) {
-        int l1 = (j0 != 0) + (j1 != 0) + (j2 != 0) + D;
-        s += ldexp(1.0, -l1) * in[state_index(G, i0 + j0, i1 + j1, i2 + j2)];
-      }
-  out[t] = s;
+  out[lin(G, i0, i1, i2)] = filter_point<D>(G, in, i0, i1, i2);
 }
 
 // ---- Jacobi sweep -----------------------------------------------------------------
@@ -141,33 +89,7 @@ template <int D>
 __global__ void k_jacobi(Geo G, const double *__restrict__ omega, const double *__restrict__ xin,
                          double *__restrict__ xout, double *part) {
   NODE_COORDS(G.n[0], G.n[1]);
-  const long t = inside ? lin(G, i0, i1, i2) : 0;
-  double r = 0.0;
-  if (inside) {
-    double w0 = omega[t];
-    double den = 0.0, num[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) num[j] = 0.0;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      int e0 = k == 0, e1 = k == 1, e2 = k == 2;
-      double h2 = G.idxi[k] * G.idxi[k];
-      double wp = 0.5 * (w0 + omega[state_index(G, i0 + e0, i1 + e1, i2 + e2)]) * h2;
-      double wm = 0.5 * (w0 + omega[state_index(G, i0 - e0, i1 - e1, i2 - e2)]) * h2;
-      den += wp + wm;
-#pragma unroll
-      for (int j = 0; j < D; ++j)
-        num[j] += wp * mesh_at(G, xin, j, i0 + e0, i1 + e1, i2 + e2, 0) +
-                  wm * mesh_at(G, xin, j, i0 - e0, i1 - e1, i2 - e2, 0);
-    }
-    double iden = 1.0 / den;
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      double v = num[j] * iden;
-      r = fmax(r, fabs(v - xin[(long)j * G.N + t]));
-      xout[(long)j * G.N + t] = v;
-    }
-  }
+  const double r = inside ? jacobi_point<D>(G, omega, xin, xout, i0, i1, i2) : 0.0;
   if (part) {
     double mr = block_max(r);
     if (flat_tid() == 0) part[flat_bid()] = mr;
@@ -178,18 +100,7 @@ __global__ void k_jacobi(Geo G, const double *__restrict__ omega, const double *
 template <int D>
 __global__ void k_limiter(Geo G, const double *__restrict__ xn, const double *__restrict__ xmu, double *part) {
   NODE_COORDS(G.n[0], G.n[1]);
-  const long t = inside ? lin(G, i0, i1, i2) : 0;
-  double g = 1.0;
-  if (inside) {
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      int e0 = k == 0, e1 = k == 1, e2 = k == 2;
-      double x0 = xn[(long)k * G.N + t];
-      double dx = xmu[(long)k * G.N + t] - x0;
-      if (dx < 0.0) g = fmin(g, -(x0 - mesh_at(G, xn, k, i0 - e0, i1 - e1, i2 - e2, 0)) / (2.0 * dx));
-      else if (dx > 0.0) g = fmin(g, (mesh_at(G, xn, k, i0 + e0, i1 + e1, i2 + e2, 0) - x0) / (2.0 * dx));
-    }
-  }
+  const double g = inside ? limiter_point<D>(G, xn, xmu, i0, i1, i2) : 1.0;
   double mg = block_min(g);
   if (flat_tid() == 0) part[flat_bid()] = mg;
 }

@@ -21,7 +21,8 @@ SYMBOLS = ["esvdw_create", "esvdw_destroy", "esvdw_get_status", "esvdw_strerror"
            "compute_metrics", "es_rhs", "rk_stage", "redistribute_mesh", "mesh_monitor", "mesh_jacobi",
            "mesh_limiter", "mesh_converged", "cfl_dt", "esvdw_step", "esvdw_bench_kernel", "mlp_features", "mlp_infer",
            "mlp_grad", "mlp_adam", "esvdw_batch_create", "esvdw_batch_destroy", "esvdw_batch_offsets",
-           "esvdw_batch_init_mesh", "esvdw_batch_init_state", "esvdw_batch_stage", "esvdw_batch_step",
+           "esvdw_batch_init_mesh", "esvdw_batch_init_state", "esvdw_batch_stage", "esvdw_batch_redistribute",
+           "esvdw_batch_step",
            "esvdw_batch_variants", "esvdw_batch_set_variant", "esvdw_batch_get_status"]
 MLP_NPARAM = 9360
 
@@ -108,6 +109,7 @@ def lib():
             "esvdw_batch_init_mesh": (I, [_VP] * 4),
             "esvdw_batch_init_state": (I, [_VP] * 5),
             "esvdw_batch_stage": (I, [_VP, I] + [_VP] * 10),
+            "esvdw_batch_redistribute": (I, [_VP] * 7),
             "esvdw_batch_step": (I, [_VP] * 7),
             "esvdw_batch_variants": (I, []),
             "esvdw_batch_set_variant": (I, [_VP, I]),
@@ -280,6 +282,10 @@ class Batch:
         _check(self.L.esvdw_batch_stage(self.h, int(s), _ptr(JU0), _ptr(J0), _ptr(JUs), _ptr(Js), _ptr(JUout),
                                         _ptr(Jout), _ptr(x), _ptr(xdot), _ptr(dt), _stream(stream)),
                "esvdw_batch_stage")
+
+    def redistribute(self, JU, J, x, xdot, dt, stream=None):
+        _check(self.L.esvdw_batch_redistribute(self.h, _ptr(JU), _ptr(J), _ptr(x), _ptr(xdot), _ptr(dt),
+                                               _stream(stream)), "esvdw_batch_redistribute")
 
     def step(self, JU, J, x, xdot, dt, stream=None):
         _check(self.L.esvdw_batch_step(self.h, _ptr(JU), _ptr(J), _ptr(x), _ptr(xdot), _ptr(dt), _stream(stream)),

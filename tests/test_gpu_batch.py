@@ -237,3 +237,90 @@ def test_batch_full_size_sampled(torch_dev):
         e = relerr(gJU[i], oU)
         print("instance %d (n = %d): rel err vs single path %.3e tol %.3e" % (i, p["n"][0], e, tol))
         assert e < tol, i
+
+
+def _moving_setup(torch, probs):
+    """Curvilinear meshes (smooth, seeded) with J and JU from the single-problem path."""
+    from paper_2407_05568_amd.esvdw import Context
+    xs, Js, JUs = [], [], []
+    for i, (p, prim) in enumerate(probs):
+        c = Context(p)
+        x = synth.smooth_mesh(p, 80 + i, amp=0.02)
+        shape = tuple(reversed(p["n"][:2]))
+        Ji = torch.empty(shape, dtype=torch.float64, device="cuda")
+        c.init_mesh(torch.from_numpy(x).cuda(), Ji, 0)
+        JUi = torch.empty((4,) + shape, dtype=torch.float64, device="cuda")
+        c.init_state(torch.from_numpy(np.ascontiguousarray(prim)).cuda(), Ji, JUi)
+        xs.append(x)
+        Js.append(Ji.cpu().numpy())
+        JUs.append(JUi.cpu().numpy())
+    return xs, Js, JUs
+
+
+def test_batch_redistribute_matches_single_path_and_oracle(orc, torch_dev):
+    """Monitor with per-instance maxima, filter, mu Jacobi sweeps, limiter, CFL and xdot of every
+    instance: against redistribute_mesh of the single-problem path (same device functions; maxima
+    and minima are exact in any order) and against the oracle (the next mesh x + dt xdot to
+    1e-13 in domain units, dt to 1e-14 relative)."""
+    torch = torch_dev
+    from paper_2407_05568_amd.esvdw import Context
+    probs = _problems()
+    B, off, shapes, _, _, _ = _batch(torch, probs)
+    xs, Js, JUs = _moving_setup(torch, probs)
+    x, J, JU = pack(torch, xs, 2, off), pack(torch, Js, 1, off), pack(torch, JUs, 4, off)
+    xd = torch.zeros_like(x)
+    dt = torch.zeros(len(probs), dtype=torch.float64, device="cuda")
+    B.redistribute(JU, J, x, xd, dt)
+    assert B.status() == 0
+    gxd, dts = unpack(xd, 2, off, shapes), dt.cpu().numpy()
+    assert np.array_equal(unpack(x, 2, off, shapes)[0], xs[0])  # x is not modified
+    for i, (p, _) in enumerate(probs):
+        c = Context(p)
+        sxd = torch.zeros((2,) + shapes[i], dtype=torch.float64, device="cuda")
+        sdt = torch.zeros(1, dtype=torch.float64, device="cuda")
+        c.redistribute_mesh(torch.from_numpy(JUs[i]).cuda(), torch.from_numpy(Js[i]).cuda(),
+                            torch.from_numpy(xs[i]).cuda(), None, sxd, sdt)
+        s = sxd.cpu().numpy()
+        assert abs(sdt.item() - dts[i]) <= 1e-15 * dts[i]
+        assert np.abs(gxd[i] - s).max() <= 1e-13 * max(np.abs(s).max(), 1e-300), i
+        r = orc.Oracle(p).redistribute(JUs[i], Js[i], xs[i])
+        assert abs(dts[i] - r["dt"]) <= 1e-14 * r["dt"]
+        nx_g = xs[i] + dts[i] * gxd[i]
+        nx_o = xs[i] + r["dt"] * r["xdot"]
+        print("instance %d: next-mesh difference to the oracle %.2e" % (i, np.abs(nx_g - nx_o).max()))
+        assert np.abs(nx_g - nx_o).max() <= 1e-13
+
+
+def test_batch_moving_step_matches_single_path(torch_dev):
+    """A full moving-mesh step of every instance (esvdw_batch_redistribute + esvdw_batch_step)
+    against esvdw_step(moving) of the single-problem path, at the conditioning bar."""
+    torch = torch_dev
+    from paper_2407_05568_amd.esvdw import Context
+    probs = _problems()
+    B, off, shapes, _, _, _ = _batch(torch, probs)
+    xs, Js, JUs = _moving_setup(torch, probs)
+    x, J, JU = pack(torch, xs, 2, off), pack(torch, Js, 1, off), pack(torch, JUs, 4, off)
+    xd = torch.zeros_like(x)
+    dt = torch.zeros(len(probs), dtype=torch.float64, device="cuda")
+    B.redistribute(JU, J, x, xd, dt)
+    B.step(JU, J, x, xd, dt)
+    assert B.status() == 0
+    gJU, gx = unpack(JU, 4, off, shapes), unpack(x, 2, off, shapes)
+    for i, (p, _) in enumerate(probs):
+        c = Context(p)
+
+        def single(U0):
+            U, Jc, X = U0.clone(), torch.from_numpy(Js[i]).cuda(), torch.from_numpy(xs[i]).cuda()
+            c.step(U, Jc, X, 1, torch.zeros(1, dtype=torch.float64, device="cuda"))
+            return U.cpu().numpy(), X.cpu().numpy()
+        U0 = torch.from_numpy(JUs[i]).cuda()
+        ref, refx = single(U0)
+        assert c.status() == 0
+        rng = np.random.default_rng(5)
+        pert = U0 * (1.0 + 2.0 ** -52 * torch.from_numpy(rng.choice([-1.0, 1.0], size=tuple(U0.shape))).cuda())
+        kappa = relerr(single(pert)[0], ref)
+        tol = max(1e-13, 8 * kappa)
+        e = relerr(gJU[i], ref)
+        print("instance %d: moving step rel err vs single path %.3e tol %.3e" % (i, e, tol))
+        assert e < tol
+        assert np.abs(gx[i] - refx).max() <= 1e-13
