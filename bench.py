@@ -177,6 +177,23 @@ def main():
     value = node_stages / (ms / 1e3)
     print("timed %d steps: %.3f ms/step, status %d" % (args.steps, ms_per_step, status), file=sys.stderr, flush=True)
 
+    # the same step on the current (fixed) mesh: CFL + three RK stages, no redistribution
+    # (separate state copy; the timed run above is unaffected)
+    JUf, Jf, xf = JU.clone(), J.clone(), x.clone()
+    dtf = torch.zeros(1, dtype=torch.float64, device=dev)
+    ctx.step(JUf, Jf, xf, 0, dtf, stream)
+    torch.cuda.synchronize()
+    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f0.record(stream)
+    for _ in range(args.steps):
+        ctx.step(JUf, Jf, xf, 0, dtf, stream)
+    f1.record(stream)
+    torch.cuda.synchronize()
+    ms_fixed = f0.elapsed_time(f1) / args.steps
+    rhs_only = {"ms_per_step": ms_fixed, "node_stages_per_s": nodes * 3 / (ms_fixed / 1e3),
+                "what": "CFL + three RK stages on the current mesh, no redistribution (direct launches)"}
+    del JUf, Jf, xf
+
     # dominant kernel: the interface-flux kernel, timed live on the same stream
     k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = args.kernel_reps
@@ -229,6 +246,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": cfg,
+        "rhs_only": rhs_only,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

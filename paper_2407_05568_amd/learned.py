@@ -2,15 +2,18 @@
 scheme's own runs, training with the library's MFMA forward/backward and Adam kernels, and
 the comparison with the plain iteration at the same final residual.
 
-A frame is the state (U^n, x^n) of a moving-mesh run with the Jacobi iteration taken to the
-tolerance mesh_tol: its inputs are the node features written by ``mlp_features`` and its
-target is the converged (pre-limiter) displacement (x^[mu] - x^n) / dxi per component.  The
+A frame is a state (U^n, x^n) of a moving-mesh run of the method (its usual fixed sweep
+count): its inputs are the node features written by ``mlp_features`` and its target is the
+converged (pre-limiter) displacement (x^[mu] - x^n) / dxi per component of the redistribution
+of that state solved to the tolerance mesh_tol.  The
 network sees only the 5 x 5 stencil of features around a node; the plain Jacobi iteration
 always finishes the solve from x^n + warm_dx to the same tolerance, so the final mesh
 residual does not depend on the network.
 
 Run as a module for the full-size experiment (prints one JSON line, progress on stderr):
-    python -m paper_2407_05568_amd.learned --size 1024 --train-steps 16 --test-steps 4
+    python -m paper_2407_05568_amd.learned --size 1024
+(frames every 5 steps of the method's own runs from 6 training seeds, 3 frames each of 2
+held-out seeds for the comparison).
 """
 import argparse
 import json
@@ -40,13 +43,23 @@ def init_params(seed):
     return P
 
 
-class Run:
-    """A moving-mesh run of one problem on the GPU, one redistribution per step in tolerance
-    mode (the Jacobi iteration runs until the largest node update is below mesh_tol)."""
+def tol_problem(p, tol):
+    """The same problem with the Jacobi iteration taken to the tolerance tol (largest node
+    update), the setting in which a warm start can shorten the solve."""
+    q = dict(p)
+    q.update(fixed_mu=0, mu=50_000_000, mesh_tol=tol)
+    return q
 
-    def __init__(self, torch, p, prim, stream=None):
+
+class Run:
+    """A moving-mesh run of one problem on the GPU: it advances with the method's own step
+    (redistribution with the problem's fixed sweep count, then three RK stages), and at frames
+    solves the redistribution of the current state to the tolerance with a second context."""
+
+    def __init__(self, torch, p, prim, tol=1e-8, stream=None):
         self.torch, self.p = torch, p
         self.ctx = Context(p)
+        self.ctx_tol = Context(tol_problem(p, tol))
         self.stream = stream or torch.cuda.current_stream()
         n = p["n"][:p["dim"]]
         shape = tuple(reversed(n))
@@ -58,9 +71,8 @@ class Run:
         self.JU = torch.empty((p["dim"] + 2,) + shape, **f64)
         self.xdot = torch.empty_like(self.x)
         self.xmu = torch.empty_like(self.x)
-        self.stage = [torch.empty_like(self.JU) for _ in range(2)]
-        self.stageJ = [torch.empty_like(self.J) for _ in range(2)]
         self.dt = torch.zeros(1, **f64)
+        self.dt_step = torch.zeros(1, **f64)
         self.res = torch.zeros(1, **f64)
         self.sweeps = torch.zeros(1, dtype=torch.int32, device="cuda")
         self.ctx.init_mesh(self.x, self.J, 1, self.stream)
@@ -69,53 +81,56 @@ class Run:
     def features(self, out):
         self.ctx.mlp_features(self.JU, self.J, out, self.stream)
 
-    def redistribute(self, warm=None):
-        """Redistribution from the current state; returns (sweeps, final residual, ms)."""
+    def solve(self, warm=None):
+        """Redistribution of the current state to the tolerance, from x^n (+ warm);
+        returns (sweeps, final residual, ms)."""
         torch = self.torch
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(self.stream)
-        self.ctx.redistribute_mesh(self.JU, self.J, self.x, warm, self.xdot, self.dt, self.res, self.sweeps,
-                                   self.stream)
+        self.ctx_tol.redistribute_mesh(self.JU, self.J, self.x, warm, self.xdot, self.dt, self.res, self.sweeps,
+                                       self.stream)
         e1.record(self.stream)
         torch.cuda.synchronize()
         return int(self.sweeps.item()), float(self.res.item()), e0.elapsed_time(e1)
 
-    def advance(self):
-        """Three SSP-RK3 stages with the mesh velocity of the last redistribution."""
-        c, s = self.ctx, self.stream
-        c.rk_stage(0, self.dt, self.JU, self.J, self.JU, self.J, self.x, self.xdot, self.stage[0], self.stageJ[0],
-                   None, s)
-        c.rk_stage(1, self.dt, self.JU, self.J, self.stage[0], self.stageJ[0], self.x, self.xdot, self.stage[1],
-                   self.stageJ[1], None, s)
-        c.rk_stage(2, self.dt, self.JU, self.J, self.stage[1], self.stageJ[1], self.x, self.xdot, self.JU, self.J,
-                   self.x, s)
-
     def target(self, out):
-        """(x^[mu] - x^n) / dxi of the last redistribution, as FP32 (dim fields)."""
-        self.ctx.mesh_converged(self.xmu, self.stream)
+        """(x^[mu] - x^n) / dxi of the last tolerance solve, as FP32 (dim fields)."""
+        self.ctx_tol.mesh_converged(self.xmu, self.stream)
         d = self.p["dim"]
         out.copy_(((self.xmu - self.x) / self.dxi.view((d,) + (1,) * d)).float())
 
+    def advance(self, steps):
+        """`steps` steps of the method (fixed sweep count); raises if the scheme flags a state."""
+        for _ in range(steps):
+            self.ctx.step(self.JU, self.J, self.x, 1, self.dt_step, self.stream)
+        st = self.ctx.status()
+        if st:
+            raise RuntimeError("scheme raised status flags %d" % st)
 
-def generate(torch, p, prim, steps, tag=""):
-    """Frames of a run: features and targets (FP32, [steps][2][N]) and per-step statistics."""
-    run = Run(torch, p, prim)
+
+def generate(torch, p, prims, frames, every, tol=1e-8, tag=""):
+    """Frames from runs of the method: for each initial state in `prims`, `frames` frames taken
+    every `every` steps (features and the converged displacement / dxi, FP32 [F][2][N]).
+    Returns (feats, tgts, per-frame statistics)."""
     shape = tuple(reversed(p["n"][:2]))
-    feats = torch.empty((steps, 2) + shape, dtype=torch.float32, device="cuda")
+    F = frames * len(prims)
+    feats = torch.empty((F, 2) + shape, dtype=torch.float32, device="cuda")
     tgts = torch.empty_like(feats)
     stats = []
-    for s in range(steps):
-        run.features(feats[s])
-        sw, res, ms = run.redistribute()
-        run.target(tgts[s])
-        run.advance()
-        st = run.ctx.status()
-        stats.append(dict(sweeps=sw, resid=res, ms=ms, flags=st))
-        _log("%sframe %d: %d sweeps, residual %.2e, %.1f ms, |target|max %.2f dxi" % (
-            tag, s, sw, res, ms, float(tgts[s].abs().max())))
-        if st:
-            raise RuntimeError("scheme raised status flags %d while generating frames" % st)
-    return run, feats, tgts, stats
+    f = 0
+    for r, prim in enumerate(prims):
+        run = Run(torch, p, prim, tol)
+        for k in range(frames):
+            run.features(feats[f])
+            sw, res, ms = run.solve()
+            run.target(tgts[f])
+            stats.append(dict(run=r, frame=k, sweeps=sw, resid=res, ms=ms))
+            _log("%srun %d frame %d: %d sweeps, residual %.2e, %.1f ms, |target|max %.2f dxi" % (
+                tag, r, k, sw, res, ms, float(tgts[f].abs().max())))
+            f += 1
+            run.advance(every)
+        del run
+    return feats, tgts, stats
 
 
 def train(torch, ctx, feats, tgts, iters=2000, batch=8192, lr=1e-3, seed=0, log_every=250):
@@ -157,77 +172,77 @@ def heldout_error(torch, ctx, P, feats, tgts, dxi):
     return (num / den) ** 0.5 if den > 0 else 0.0
 
 
-def compare(torch, run, P, steps, tag=""):
-    """Advance `run` by `steps` steps; at each, time the plain redistribution (x^[0] = x^n)
-    and the warm-started one (features + inference + the same iteration from x^n + warm_dx),
-    both to mesh_tol.  The run itself advances with the plain result."""
+def compare(torch, run, P, frames, every, tag=""):
+    """At `frames` frames of `run`, `every` steps apart: time the plain solve (x^[0] = x^n) and
+    the warm-started one (features + inference + the same iteration from x^n + warm_dx), both
+    to the tolerance.  The run advances with the method's own step between frames."""
     shape = tuple(reversed(run.p["n"][:2]))
     feat = torch.empty((2,) + shape, dtype=torch.float32, device="cuda")
     warm = torch.empty((2,) + shape, dtype=torch.float64, device="cuda")
     out = []
-    for s in range(steps):
+    for k in range(frames):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(run.stream)
         run.features(feat)
         run.ctx.mlp_infer(feat, P, warm, run.stream)
         e1.record(run.stream)
-        sw_w, res_w, ms_w = run.redistribute(warm)
+        sw_w, res_w, ms_w = run.solve(warm)
         torch.cuda.synchronize()
         ms_inf = e0.elapsed_time(e1)
-        sw_p, res_p, ms_p = run.redistribute()
-        run.advance()
-        st = run.ctx.status()
-        if st:
-            raise RuntimeError("scheme raised status flags %d during the comparison run" % st)
+        sw_p, res_p, ms_p = run.solve()
         rec = dict(plain_sweeps=sw_p, plain_resid=res_p, plain_ms=ms_p, warm_sweeps=sw_w, warm_resid=res_w,
                    warm_ms=ms_w + ms_inf, infer_ms=ms_inf)
         out.append(rec)
-        _log("%sstep %d: plain %d sweeps %.1f ms (res %.1e) | warm %d sweeps %.1f ms (+%.2f ms net, res %.1e)" % (
-            tag, s, sw_p, ms_p, res_p, sw_w, ms_w, ms_inf, res_w))
+        _log("%sframe %d: plain %d sweeps %.1f ms (res %.1e) | warm %d sweeps %.1f ms (+%.2f ms net, res %.1e)" % (
+            tag, k, sw_p, ms_p, res_p, sw_w, ms_w, ms_inf, res_w))
+        run.advance(every)
     return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--size", type=int, default=1024)
-    ap.add_argument("--train-steps", type=int, default=16)
-    ap.add_argument("--test-steps", type=int, default=4)
-    ap.add_argument("--iters", type=int, default=2000)
+    ap.add_argument("--train-seeds", default="0,4,5,11,13,14")
+    ap.add_argument("--test-seeds", default="2,19")
+    ap.add_argument("--frames", type=int, default=6)
+    ap.add_argument("--test-frames", type=int, default=3)
+    ap.add_argument("--every", type=int, default=5)
+    ap.add_argument("--iters", type=int, default=3000)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--test-seed", type=int, default=2)
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available(), "the learned warm start runs on the GPU"
     n = args.size
-    p = synth.problem(2, [n, n], bc="outflow", fixed_mu=0, mu=50_000_000, mesh_tol=args.tol)
+    p = synth.problem(2, [n, n], bc="outflow")
+    seeds = [int(v) for v in args.train_seeds.split(",")]
+    tests = [int(v) for v in args.test_seeds.split(",")]
     t0 = time.time()
-    prim = synth.quadrants_2d(p, synth.quadrant_states(p, args.seed))
-    run, feats, tgts, gstats = generate(torch, p, prim, args.train_steps, "train ")
+    prims = [synth.quadrants_2d(p, synth.quadrant_states(p, sd)) for sd in seeds]
+    feats, tgts, gstats = generate(torch, p, prims, args.frames, args.every, args.tol, "train ")
     t_gen = time.time() - t0
+    ctx = Context(p)
+    dxi = torch.tensor([1.0 / n, 1.0 / n], dtype=torch.float64, device="cuda")
     t0 = time.time()
-    P, hist = train(torch, run.ctx, feats, tgts, args.iters, args.batch, args.lr, args.seed)
+    P, hist = train(torch, ctx, feats, tgts, args.iters, args.batch, args.lr, seeds[0])
     torch.cuda.synchronize()
     t_train = time.time() - t0
-    err_train = heldout_error(torch, run.ctx, P, feats, tgts, run.dxi)
+    err_train = heldout_error(torch, ctx, P, feats, tgts, dxi)
     _log("training frames: relative displacement error %.3f" % err_train)
-    # same run, later steps (in distribution) and a run from other quadrant states
-    same = compare(torch, run, P, args.test_steps, "same-run ")
-    prim2 = synth.quadrants_2d(p, synth.quadrant_states(p, args.test_seed))
-    run2 = Run(torch, p, prim2)
-    other = compare(torch, run2, P, args.test_steps, "other-run ")
-
-    def agg(recs):
-        ps, ws = sum(r["plain_ms"] for r in recs), sum(r["warm_ms"] for r in recs)
-        return dict(plain_ms=ps, warm_ms=ws, speedup=ps / ws if ws > 0 else None,
-                    plain_sweeps=sum(r["plain_sweeps"] for r in recs), warm_sweeps=sum(r["warm_sweeps"] for r in recs),
-                    max_final_resid=max(max(r["plain_resid"], r["warm_resid"]) for r in recs))
-    out = dict(size=n, tol=args.tol, train_steps=args.train_steps, iters=args.iters, batch=args.batch,
-               gen_s=t_gen, train_s=t_train, loss=hist, train_rel_err=err_train,
-               same_run=agg(same), other_run=agg(other), steps_same=same, steps_other=other, gen=gstats)
+    del feats, tgts
+    recs = []
+    for sd in tests:
+        run = Run(torch, p, synth.quadrants_2d(p, synth.quadrant_states(p, sd)), args.tol)
+        recs += compare(torch, run, P, args.test_frames, args.every, "held-out seed %d " % sd)
+        del run
+    ps, ws = sum(r["plain_ms"] for r in recs), sum(r["warm_ms"] for r in recs)
+    out = dict(size=n, tol=args.tol, train_seeds=seeds, test_seeds=tests, frames_per_run=args.frames,
+               every=args.every, iters=args.iters, batch=args.batch, gen_s=t_gen, train_s=t_train, loss=hist,
+               train_rel_err=err_train, plain_ms=ps, warm_ms=ws, speedup=ps / ws if ws > 0 else None,
+               plain_sweeps=sum(r["plain_sweeps"] for r in recs), warm_sweeps=sum(r["warm_sweeps"] for r in recs),
+               max_final_resid=max(max(r["plain_resid"], r["warm_resid"]) for r in recs), frames=recs, gen=gstats)
     line = json.dumps(out)
     print(line, flush=True)
     if args.out:
