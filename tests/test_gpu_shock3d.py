@@ -1,0 +1,150 @@
+"""The 3D spherically symmetric shock tube (Example 5.7) on the moving mesh, GPU against the
+oracle: the adaptation of the initial mesh (redistribution passes on the initial data), one
+RK stage on the adapted mesh, several full steps, and the invariants of a run to the final
+time.
+
+Bars: the mesh passes and the single stage are compared at max(1e-12, 8 kappa); the multi-step
+run at max(1e-9, 8 kappa), with kappa the oracle's own change under a 1-ulp perturbation of its
+input.  On this data kappa is large after one step (~1e-5 relative): next to the sphere the
+sign test of the dissipation meets real jumps that are tiny, and which side of zero they fall on
+decides whether a full reconstructed jump is dissipated, so rounding-level differences become
+O(1e-5) within a step, in the oracle as much as between oracle and GPU."""
+import numpy as np
+import pytest
+
+from paper_2407_05568_amd import shock3d, synth
+
+pytestmark = pytest.mark.gpu
+
+N, PASSES = 16, 20
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2407_05568_amd import esvdw
+    esvdw.lib()
+    return torch
+
+
+def relerr(g, r):
+    g = np.asarray(g).reshape(np.shape(g)[0], -1)
+    r = np.asarray(r).reshape(g.shape)
+    return max(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300) for a, b in zip(g, r))
+
+
+def ulp_perturb(a, seed):
+    rng = np.random.default_rng(seed)
+    return a * (1.0 + 2.0 ** -52 * rng.choice([-1.0, 1.0], size=a.shape))
+
+
+def oracle_preadapt(o, p, x, passes):
+    for _ in range(passes):
+        J = o.jacobian(x)
+        JU = o.init_state(synth.spherical_shock_3d(p, x), J)
+        r = o.redistribute(JU, J, x)
+        x = x + r["xdot"] * r["dt"]
+    J = o.jacobian(x)
+    return x, J, o.init_state(synth.spherical_shock_3d(p, x), J)
+
+
+@pytest.fixture(scope="module")
+def adapted(orc):
+    p = shock3d.problem(N)
+    o = orc.Oracle(p)
+    x0 = o.uniform_mesh()
+    x, J, JU = oracle_preadapt(o, p, x0, PASSES)
+    xp, _, _ = oracle_preadapt(o, p, ulp_perturb(x0, 3), PASSES)
+    assert o.flags() == 0
+    return p, o, x0, x, J, JU, np.abs(xp - x).max()
+
+
+def test_spherical_shock_initial_mesh_matches_oracle(torch_dev, adapted):
+    torch = torch_dev
+    from paper_2407_05568_amd.esvdw import Context
+    p, o, x0, x, J, JU, kappa = adapted
+    ctx = Context(p)
+    xg = torch.from_numpy(x0.copy()).cuda()
+    Jg = torch.empty(o.shape, dtype=torch.float64, device="cuda")
+    JUg = torch.empty((5,) + o.shape, dtype=torch.float64, device="cuda")
+    done, move = shock3d.preadapt(torch, ctx, p, xg, Jg, JUg, PASSES, tol=0.0)
+    torch.cuda.synchronize()
+    tol = max(1e-12, 8 * kappa)
+    ex = np.abs(xg.cpu().numpy() - x).max()
+    eJ = np.abs(Jg.cpu().numpy() - J).max()
+    eU = relerr(JUg.cpu().numpy(), JU)
+    print("initial mesh %d^3, %d passes (last move %.3f cells): x err %.2e J err %.2e JU rel err %.2e tol %.2e" % (
+        N, done, move, ex, eJ, eU, tol))
+    assert done == PASSES
+    assert ex < tol and eJ < tol and eU < tol
+    assert ctx.status() == 0
+
+
+def test_spherical_shock_first_stage_matches_oracle(torch_dev, adapted):
+    """Redistribution and the first SSP-RK3 stage on the adapted mesh, from identical inputs."""
+    torch = torch_dev
+    from paper_2407_05568_amd.esvdw import Context
+    p, o, x0, x, J, JU, _ = adapted
+    r = o.redistribute(JU, J, x)
+    JU1, J1 = o.rk_stage(0, r["dt"], JU, J, JU, J, x, r["xdot"])
+    JUq = ulp_perturb(JU, 5)
+    rq = o.redistribute(JUq, J, x)
+    JU1q, J1q = o.rk_stage(0, rq["dt"], JUq, J, JUq, J, x, rq["xdot"])
+    kappa = max(relerr(JU1q / J1q[None], JU1 / J1[None]), relerr(rq["xdot"], r["xdot"]))
+    ctx = Context(p)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    xg, Jg, JUg = T(x), T(J), T(JU)
+    xdot = torch.empty_like(xg)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.redistribute_mesh(JUg, Jg, xg, None, xdot, dt)
+    JU1g, J1g = torch.empty_like(JUg), torch.empty_like(Jg)
+    ctx.rk_stage(0, dt, JUg, Jg, JUg, Jg, xg, xdot, JU1g, J1g)
+    torch.cuda.synchronize()
+    tol = max(1e-12, 8 * kappa)
+    ed = abs(float(dt.item()) - r["dt"]) / r["dt"]
+    ev = relerr(xdot.cpu().numpy(), r["xdot"])
+    eu = relerr((JU1g / J1g[None]).cpu().numpy(), JU1 / J1[None])
+    print("first stage %d^3: dt err %.2e xdot err %.2e U err %.2e kappa %.2e tol %.2e" % (N, ed, ev, eu, kappa, tol))
+    assert ed < tol and ev < tol and eu < tol
+    assert ctx.status() == 0 and o.flags() == 0
+
+
+def test_spherical_shock_steps_match_oracle(torch_dev, adapted):
+    torch = torch_dev
+    from paper_2407_05568_amd.esvdw import Context
+    p, o, x0, x, J, JU, _ = adapted
+    steps = 6
+    ctx = Context(p)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    xg, Jg, JUg = T(x), T(J), T(JU)
+    dtg = torch.zeros(1, dtype=torch.float64, device="cuda")
+    JUp, Jp, xp = ulp_perturb(JU, 7), J.copy(), x.copy()
+    for _ in range(steps):
+        JU, J, x, _ = o.step(JU, J, x, moving=True)
+        JUp, Jp, xp, _ = o.step(JUp, Jp, xp, moving=True)
+        ctx.step(JUg, Jg, xg, 1, dtg)
+    torch.cuda.synchronize()
+    kappa = max(relerr(JUp / Jp[None], JU / J[None]), np.abs(xp - x).max())
+    tol = max(1e-9, 8 * kappa)
+    eu = relerr((JUg / Jg[None]).cpu().numpy(), JU / J[None])
+    ex = np.abs(xg.cpu().numpy() - x).max()
+    print("spherical shock %d^3, %d steps: U rel err %.3e x err %.3e kappa %.3e tol %.3e" % (N, steps, eu, ex, kappa, tol))
+    assert eu < tol and ex < tol
+    assert ctx.status() == 0 and o.flags() == 0
+
+
+def test_spherical_shock_invariants(torch_dev):
+    """32^3 to the final time: no status flags, the final time reached, the mirror symmetries of
+    the data kept, density within the range of the two initial states (up to the small
+    overshoots of the scheme), mass changed only by what crosses the outflow faces."""
+    torch = torch_dev
+    out = shock3d.run(torch, 32)
+    print("32^3: %d passes, %d steps, t %.4f, mass drift %.2e, mirror %.2e, permutation %.2e, rho [%.3f, %.3f]" % (
+        out["preadapt_passes"], out["steps"], out["t"], out["mass_drift"], out["mirror_err"], out["permutation_err"],
+        out["rho_min"], out["rho_max"]))
+    assert out["flags"] == 0
+    assert out["t"] >= shock3d.T_END
+    assert abs(out["mass_drift"]) < 1e-3
+    assert out["mirror_err"] < 5e-3
+    assert 0.2 < out["rho_min"] and out["rho_max"] < 1.9
