@@ -142,6 +142,16 @@ int redistribute_mesh(esvdw_ctx *ctx, const double *JU, const double *J, const d
 int mesh_monitor(esvdw_ctx *ctx, const double *JU, const double *J, double *omega, hipStream_t stream);
 int mesh_jacobi(esvdw_ctx *ctx, const double *omega, double *x, int nsweep, double *resid_dev,
                 hipStream_t stream);
+/* Red-black successive over-relaxation for the same discretised eq. mesh_EL (Section 4) as
+ * mesh_jacobi, with the same fixed point: an alternative solver for the mesh iteration
+ * (Gauss-Seidel for relax = 1).  A sweep updates the nodes with i0 + i1 + i2 even, then the odd
+ * ones, in place; each node solves its own equation with the other colour held fixed (at an
+ * outflow wall its mirror image is itself: normal coordinate 2 wall - x, tangential x) and moves
+ * to x + relax (v - x).  nsweep sweeps on x (dim fields) with fixed omega; *resid_dev = the
+ * largest |v - x| of the last sweep (may be NULL).  ESVDW_EINVAL unless 0 < relax < 2 and every
+ * periodic direction has an even node count (the wrap must join opposite colours). */
+int mesh_sor(esvdw_ctx *ctx, const double *omega, double *x, int nsweep, double relax, double *resid_dev,
+             hipStream_t stream);
 int mesh_limiter(esvdw_ctx *ctx, const double *x_n, const double *x_mu, double *gamma_dev, hipStream_t stream);
 /* mesh_converged: copies into xmu_out (dim fields) the Jacobi result x^[mu] of the last
  *   redistribute_mesh call on this context, before the movement limiter (Section 4); the

@@ -114,6 +114,7 @@ def lib():
             "orc_monitor": (None, [_CP, _D, _D, _D]),
             "orc_filter": (None, [_CP, _D, ctypes.c_int]),
             "orc_jacobi": (ctypes.c_int, [_CP, _D, _D, ctypes.c_int, ctypes.c_double, _D]),
+            "orc_sor": (ctypes.c_int, [_CP, _D, _D, ctypes.c_int, ctypes.c_double, _D]),
             "orc_limiter": (ctypes.c_double, [_CP, _D, _D]),
             "orc_redistribute": (None, [_CP, _D, _D, _D, _D, _D, _D, _D, _D,
                                         ctypes.POINTER(ctypes.c_int), _D, _D]),
@@ -272,6 +273,16 @@ class Oracle:
         res = np.zeros(1)
         it = self.L.orc_jacobi(self._cp(), _p(_arr(omega)), _p(xx), int(nsweep), float(tol), _p(res))
         return xx, it, res[0]
+
+    def sor(self, omega, x, nsweep, relax=1.0):
+        """Red-black SOR sweeps (Gauss-Seidel for relax = 1); returns (x, resid).  Raises for a
+        periodic direction with an odd node count."""
+        xx = _arr(x).copy()
+        res = np.zeros(1)
+        it = self.L.orc_sor(self._cp(), _p(_arr(omega)), _p(xx), int(nsweep), float(relax), _p(res))
+        if it < 0:
+            raise ValueError("red-black ordering needs an even node count in periodic directions")
+        return xx, res[0]
 
     def limiter(self, xn, xmu):
         return self.L.orc_limiter(self._cp(), _p(_arr(xn)), _p(_arr(xmu)))

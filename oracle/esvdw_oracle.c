@@ -1194,6 +1194,71 @@ int orc_jacobi(const orc_cfg *c, const double *omega, double *x, int nsweep, dou
   return it;
 }
 
+/* Red-black successive over-relaxation for the same discrete mesh equations (an alternative
+ * to the Jacobi iteration above with the same fixed point; Gauss-Seidel when relax = 1).
+ * A sweep is two half-sweeps: first the nodes with i0 + i1 + i2 even, then the odd ones.  In a
+ * half-sweep every node of that colour solves its own equation for its own value, the other
+ * colour held fixed: at an outflow wall the mirror image of the node is the node itself
+ * (normal coordinate 2 wall - x, tangential x), so that term moves to the left-hand side,
+ *   normal:     (den + w) x = rest + 2 wall w,     tangential: (den - w) x = rest,
+ * and elsewhere the solve is the Jacobi value v.  Then x <- x + relax (v - x).  Periodic
+ * directions need an even node count (the wrap would join two nodes of one colour); returns -1
+ * then.  Exactly nsweep sweeps; *resid = the largest |v - x| (unrelaxed) of the last sweep.
+ * Returns the number of sweeps. */
+int orc_sor(const orc_cfg *c, const double *omega, double *x, int nsweep, double relax, double *resid) {
+  int d = c->dim;
+  long N = nodes(c);
+  for (int k = 0; k < d; ++k)
+    if (c->bc[k] == BC_PERIODIC && c->n[k] % 2) return -1;
+  pad_t p1 = make_pad(c, 1);
+  double *w = calloc(p1.N, sizeof(double));
+  to_pad(c, &p1, omega, w);
+  fill_ghosts(c, &p1, w, 3, 0);
+  double res = 0.0;
+  for (int it = 0; it < nsweep; ++it) {
+    res = 0.0;
+    for (int colour = 0; colour < 2; ++colour) {
+      double **xp = pad_mesh(c, &p1, x, 1);
+      for (int i2 = 0; i2 < p1.n[2]; ++i2)
+        for (int i1 = 0; i1 < p1.n[1]; ++i1)
+          for (int i0 = 0; i0 < p1.n[0]; ++i0) {
+            if ((i0 + i1 + i2) % 2 != colour) continue;
+            long qp = pidx(&p1, i0, i1, i2), qi = iidx(c, i0, i1, i2);
+            double den[3] = {0, 0, 0}, num[3] = {0, 0, 0};
+            for (int k = 0; k < d; ++k) {
+              double h2 = dxi(c, k) * dxi(c, k);
+              for (int side = 0; side < 2; ++side) {
+                int in[3] = {i0, i1, i2};
+                in[k] += side ? 1 : -1;
+                long qn = pidx(&p1, in[0], in[1], in[2]);
+                double wf = 0.5 * (w[qp] + w[qn]) / h2;
+                int self = c->bc[k] != BC_PERIODIC && (in[k] < 0 || in[k] >= c->n[k]);
+                for (int j = 0; j < d; ++j) {
+                  if (!self) {
+                    den[j] += wf;
+                    num[j] += wf * xp[j][qn];
+                  } else if (j == k) {
+                    den[j] += 2.0 * wf;
+                    num[j] += wf * 2.0 * (side ? c->hi[k] : c->lo[k]);
+                  }
+                  /* tangential self term: w x on both sides, dropped */
+                }
+              }
+            }
+            for (int j = 0; j < d; ++j) {
+              double v = num[j] / den[j], old = x[j * N + qi];
+              if (fabs(v - old) > res) res = fabs(v - old);
+              x[j * N + qi] = old + relax * (v - old);
+            }
+          }
+      free_fields(xp, d);
+    }
+  }
+  if (resid) *resid = res;
+  free(w);
+  return nsweep;
+}
+
 /* movement limiter: Delta_gamma = min(1, min over nodes and directions of the bound
  * -(x_k(i) - x_k(i - e_k))/(2 dx_k) if dx_k < 0, (x_k(i + e_k) - x_k(i))/(2 dx_k) if dx_k > 0),
  * dx = xmu - xn; neighbours from the ghost-extended x^n. */

@@ -201,6 +201,14 @@ int mesh_jacobi(esvdw_ctx *c, const double *omega, double *x, int nsweep, double
   return launch_jacobi(c, omega, x, nsweep, resid_dev, st) ? ESVDW_EHIP : ESVDW_OK;
 }
 
+int mesh_sor(esvdw_ctx *c, const double *omega, double *x, int nsweep, double relax, double *resid_dev,
+             hipStream_t st) {
+  if (!c || !omega || !x || nsweep < 0 || !(relax > 0.0 && relax < 2.0)) return ESVDW_EINVAL;
+  for (int k = 0; k < c->G.dim; ++k)
+    if (c->G.bc[k] == ESVDW_BC_PERIODIC && c->G.n[k] % 2) return ESVDW_EINVAL;
+  return launch_sor(c, omega, x, nsweep, relax, resid_dev, st) ? ESVDW_EHIP : ESVDW_OK;
+}
+
 int mesh_limiter(esvdw_ctx *c, const double *x_n, const double *x_mu, double *gamma_dev, hipStream_t st) {
   if (!c || !x_n || !x_mu || !gamma_dev) return ESVDW_EINVAL;
   return launch_limiter(c, x_n, x_mu, gamma_dev, st) ? ESVDW_EHIP : ESVDW_OK;

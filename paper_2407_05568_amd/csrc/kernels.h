@@ -20,6 +20,8 @@ int launch_set_int(int *p, int v, hipStream_t st);
 int launch_set_scalars(esvdw_ctx *c, hipStream_t st);
 int launch_monitor(esvdw_ctx *c, const double *JU, const double *J, double *omega, hipStream_t st);
 int launch_jacobi(esvdw_ctx *c, const double *omega, double *x, int nsweep, double *resid_dev, hipStream_t st);
+int launch_sor(esvdw_ctx *c, const double *omega, double *x, int nsweep, double relax, double *resid_dev,
+               hipStream_t st);
 int launch_limiter(esvdw_ctx *c, const double *xn, const double *xmu, double *gamma_dev, hipStream_t st);
 int launch_cfl(esvdw_ctx *c, const double *JU, const double *J, const double *x, double *dt_dev, hipStream_t st);
 int launch_xdot(esvdw_ctx *c, const double *xn, const double *xmu, const double *gam, const double *dtp, double *xdot,

@@ -96,6 +96,64 @@ __global__ void k_jacobi(Geo G, const double *__restrict__ omega, const double *
   }
 }
 
+// ---- red-black SOR half-sweep ---------------------------------------------------------
+// Nodes of one colour (i0 + i1 + i2 = colour mod 2), in place.  Thread t of a row takes
+// i0 = 2 t + ((i1 + i2 + colour) & 1).  Each node solves its own equation with the other colour
+// fixed: a neighbour across an outflow wall is the node's own mirror image (normal coordinate
+// 2 wall - x, tangential x), whose term moves to the left-hand side; every other neighbour
+// (including a periodic wrap, which needs even node counts so that it joins opposite colours)
+// is read as in the Jacobi sweep.  x <- x + relax (v - x); partial maxima of |v - x|.
+template <int D>
+__global__ void k_sor(Geo G, const double *__restrict__ omega, double *__restrict__ x, int colour, double relax,
+                      double *part) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x, i1 = blockIdx.y * blockDim.y + threadIdx.y,
+            i2 = blockIdx.z;
+  const int i0 = 2 * t + ((i1 + i2 + colour) & 1);
+  double r = 0.0;
+  if (i0 < G.n[0] && i1 < G.n[1]) {
+    const long q = lin(G, i0, i1, i2);
+    const double w0 = omega[q];
+    const int ii[3] = {i0, i1, i2};
+    double den[D], num[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) den[j] = num[j] = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const int e0 = k == 0, e1 = k == 1, e2 = k == 2;
+      const double h2 = G.idxi[k] * G.idxi[k];
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        const int sg = side ? 1 : -1;
+        const int n0 = i0 + sg * e0, n1 = i1 + sg * e1, n2 = i2 + sg * e2;
+        const double wf = 0.5 * (w0 + omega[state_index(G, n0, n1, n2)]) * h2;
+        const int ik = ii[k] + sg;
+        const bool self = G.bc[k] != ESVDW_BC_PERIODIC && (ik < 0 || ik >= G.n[k]);
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          if (!self) {
+            den[j] += wf;
+            num[j] += wf * mesh_at(G, x, j, n0, n1, n2, 0);
+          } else if (j == k) {
+            den[j] += 2.0 * wf;
+            num[j] += wf * 2.0 * (side ? G.hi[k] : G.lo[k]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const double old = x[(long)j * G.N + q];
+      const double v = num[j] / den[j];
+      r = fmax(r, fabs(v - old));
+      x[(long)j * G.N + q] = old + relax * (v - old);
+    }
+  }
+  if (part) {
+    double mr = block_max(r);
+    if (flat_tid() == 0) part[flat_bid()] = mr;
+  }
+}
+
 // ---- limiter ----------------------------------------------------------------------
 template <int D>
 __global__ void k_limiter(Geo G, const double *__restrict__ xn, const double *__restrict__ xmu, double *part) {
@@ -204,6 +262,32 @@ static int jacobi_d(esvdw_ctx *c, const double *omega, double *x, int nsweep, do
   if (a != x) launch_copy(a, x, (long)D * G.N, st);
   if (resid_dev) launch_copy(c->scal + SC_RESID, resid_dev, 1, st);
   return CHK();
+}
+
+template <int D>
+static int sor_d(esvdw_ctx *c, const double *omega, double *x, int nsweep, double relax, double *resid_dev,
+                 hipStream_t st) {
+  const Geo &G = c->G;
+  dim3 b, g;
+  node_grid((G.n[0] + 1) / 2, G.n[1], G.n[2], g, b);
+  const long nb = (long)g.x * g.y * g.z;  // 2 nb <= 4 npart: both halves' partial maxima fit
+  for (int it = 0; it < nsweep; ++it) {
+    bool last = it == nsweep - 1;
+    for (int colour = 0; colour < 2; ++colour)
+      hipLaunchKernelGGL(k_sor<D>, g, b, 0, st, G, omega, x, colour, relax, last ? c->part + colour * nb : nullptr);
+    if (last) hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, c->part, 2 * nb, c->scal + SC_RESID, 0);
+  }
+  if (resid_dev && nsweep > 0) launch_copy(c->scal + SC_RESID, resid_dev, 1, st);
+  return CHK();
+}
+
+int launch_sor(esvdw_ctx *c, const double *omega, double *x, int nsweep, double relax, double *resid_dev,
+               hipStream_t st) {
+  switch (c->G.dim) {
+    case 1: return sor_d<1>(c, omega, x, nsweep, relax, resid_dev, st);
+    case 2: return sor_d<2>(c, omega, x, nsweep, relax, resid_dev, st);
+    default: return sor_d<3>(c, omega, x, nsweep, relax, resid_dev, st);
+  }
 }
 
 int launch_jacobi(esvdw_ctx *c, const double *omega, double *x, int nsweep, double *resid_dev, hipStream_t st) {

@@ -18,7 +18,7 @@ MONVAR = {"rho": 0, "G": 1}
 
 # entry points declared in include/esvdw.h
 SYMBOLS = ["esvdw_create", "esvdw_destroy", "esvdw_get_status", "esvdw_strerror", "init_mesh", "init_state",
-           "compute_metrics", "es_rhs", "rk_stage", "redistribute_mesh", "mesh_monitor", "mesh_jacobi",
+           "compute_metrics", "es_rhs", "rk_stage", "redistribute_mesh", "mesh_monitor", "mesh_jacobi", "mesh_sor",
            "mesh_limiter", "mesh_converged", "cfl_dt", "esvdw_step", "esvdw_bench_kernel", "mlp_features", "mlp_infer",
            "mlp_grad", "mlp_adam", "esvdw_batch_create", "esvdw_batch_destroy", "esvdw_batch_offsets",
            "esvdw_batch_init_mesh", "esvdw_batch_init_state", "esvdw_batch_stage", "esvdw_batch_redistribute",
@@ -94,6 +94,7 @@ def lib():
             "redistribute_mesh": (I, [_VP] * 10),
             "mesh_monitor": (I, [_VP] * 5),
             "mesh_jacobi": (I, [_VP, _VP, _VP, I, _VP, _VP]),
+            "mesh_sor": (I, [_VP, _VP, _VP, I, ctypes.c_double, _VP, _VP]),
             "mesh_limiter": (I, [_VP] * 5),
             "mesh_converged": (I, [_VP] * 3),
             "cfl_dt": (I, [_VP] * 6),
@@ -207,6 +208,10 @@ class Context:
     def mesh_jacobi(self, omega, x, nsweep, resid_dev=None, stream=None):
         _check(self.L.mesh_jacobi(self.h, _ptr(omega), _ptr(x), int(nsweep), _ptr(resid_dev), _stream(stream)),
                "mesh_jacobi")
+
+    def mesh_sor(self, omega, x, nsweep, relax, resid_dev=None, stream=None):
+        _check(self.L.mesh_sor(self.h, _ptr(omega), _ptr(x), int(nsweep), float(relax), _ptr(resid_dev),
+                               _stream(stream)), "mesh_sor")
 
     def mesh_limiter(self, x_n, x_mu, gamma_dev, stream=None):
         _check(self.L.mesh_limiter(self.h, _ptr(x_n), _ptr(x_mu), _ptr(gamma_dev), _stream(stream)), "mesh_limiter")

@@ -214,6 +214,101 @@ def test_uniform_monitor_is_a_fixed_point(orc):
     assert np.abs(x - xi).max() < 1e-15
 
 
+def _mesh_case(orc, dim, bc, n, seed):
+    p = synth.problem(dim, n, bc=bc)
+    o = orc.Oracle(p)
+    rng = np.random.default_rng(seed)
+    xi = synth.nodes_xi(p)
+    omega = 1.0 + 3.0 * rng.random(o.shape)
+    x0 = synth.smooth_mesh(p, seed, amp=0.02)
+    return o, xi, omega, x0
+
+
+@pytest.mark.parametrize("dim,bc,n", [(1, "outflow", [14]), (2, "outflow", [12, 10]), (2, "periodic", [12, 10]),
+                                      (3, "outflow", [8, 6, 6]), (3, "periodic", [8, 6, 6])])
+@pytest.mark.parametrize("relax", [1.0, 1.7])
+def test_sor_half_sweeps_solve_each_node_equation(orc, dim, bc, n, relax):
+    """One red-black sweep: each even node (i0 + i1 + i2 even) moves to x0 + relax (v - x0) where v
+    solves its own discrete equation with the odd nodes at x0; then each odd node likewise with
+    the even nodes at their new values.  "Solves its own equation" is checked with the Jacobi
+    sweep (pinned separately): one Jacobi update leaves v unchanged at that node.  Away from
+    outflow walls v is the Jacobi value itself."""
+    o, xi, omega, x0 = _mesh_case(orc, dim, bc, n, 3)
+    idx = np.indices(o.shape).sum(0) % 2
+    even, odd = idx == 0, idx == 1
+    got, res = o.sor(omega, x0, 1, relax)
+    z = x0.copy()
+    z[:, even] = x0[:, even] + (got[:, even] - x0[:, even]) / relax
+    zj, _, _ = o.jacobi(omega, z, 1)
+    assert np.abs(zj[:, even] - z[:, even]).max() < 1e-13
+    y = got.copy()
+    y[:, odd] = x0[:, odd] + (got[:, odd] - x0[:, odd]) / relax
+    yj, _, _ = o.jacobi(omega, y, 1)
+    assert np.abs(yj[:, odd] - y[:, odd]).max() < 1e-13
+    # away from outflow walls: the plain Jacobi value of the mesh at the start of the half-sweep
+    inner = np.ones(o.shape, dtype=bool)
+    for k in range(dim):
+        if bc == "outflow":
+            ax = dim - 1 - k
+            sl = [slice(None)] * dim
+            sl[ax] = 0
+            inner[tuple(sl)] = False
+            sl[ax] = -1
+            inner[tuple(sl)] = False
+    xj, _, _ = o.jacobi(omega, x0, 1)
+    m = even & inner
+    assert np.abs(z[:, m] - xj[:, m]).max() < 1e-13
+    assert 0 < res
+
+
+@pytest.mark.parametrize("relax", [1.0, 1.8])
+def test_sor_1d_converges_to_equidistribution(orc, relax):
+    """Same fixed point as the Jacobi iteration: the closed-form equidistributed 1D mesh."""
+    n = 24
+    p = synth.problem(1, [n], bc="outflow")
+    o = orc.Oracle(p)
+    xi = synth.nodes_xi(p)
+    omega = 1.0 + 2.0 * np.exp(-((xi[0] - 0.4) / 0.1) ** 2)
+    x, res = o.sor(omega, xi.copy(), 3000, relax)
+    wf = 0.5 * (omega[1:] + omega[:-1])
+    gaps = np.concatenate([[0.5 / omega[0]], 1.0 / wf, [0.5 / omega[-1]]])
+    want = np.cumsum(gaps / gaps.sum())[:-1]
+    assert np.abs(x[0] - want).max() < 1e-10
+
+
+def test_sor_2d_fixed_point_equals_jacobi_and_is_faster(orc):
+    """Nonuniform omega on a 2D outflow grid: SOR (relax 1.8) and the Jacobi iteration converge to
+    the same mesh, SOR in fewer sweeps; Gauss-Seidel (relax 1) needs about half the Jacobi sweeps
+    (its asymptotic rate is the square of Jacobi's for this consistently ordered stencil)."""
+    o, xi, omega, x0 = _mesh_case(orc, 2, "outflow", [16, 12], 5)
+    xj, itj, _ = o.jacobi(omega, x0, 200000, tol=1e-13)
+    xs, _ = o.sor(omega, x0, 2000, 1.8)
+    assert np.abs(xs - xj).max() < 1e-10
+
+    def sweeps_to(relax, tol):
+        x, k = x0.copy(), 0
+        while True:
+            x, r = o.sor(omega, x, 1, relax)
+            k += 1
+            if r < tol:
+                return k
+    gs, sor = sweeps_to(1.0, 1e-10), sweeps_to(1.8, 1e-10)
+    _, itj10, _ = o.jacobi(omega, x0, 200000, tol=1e-10)
+    assert 0.35 * itj10 < gs < 0.65 * itj10
+    assert sor < gs / 3
+
+
+def test_sor_uniform_monitor_fixed_point_and_odd_periodic(orc):
+    p = synth.problem(2, [12, 10], bc="outflow")
+    o = orc.Oracle(p)
+    xi = synth.nodes_xi(p)
+    x, _ = o.sor(np.ones((10, 12)), xi, 5, 1.5)
+    assert np.abs(x - xi).max() < 1e-15
+    q = orc.Oracle(synth.problem(2, [13, 10], bc="periodic"))
+    with pytest.raises(ValueError):
+        q.sor(np.ones((10, 13)), synth.nodes_xi(q.p), 1)
+
+
 def test_limiter_prevents_tangling(orc):
     """x^{n+1} = x^n + Delta_gamma (x^[mu] - x^n) keeps every coordinate line monotone."""
     p = synth.problem(2, [16, 16], bc="outflow")
