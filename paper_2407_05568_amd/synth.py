@@ -328,23 +328,35 @@ def smooth_3d(p, seed, x=None):
     return np.ascontiguousarray(prim)
 
 
-def spherical_shock_3d(p, x=None, r0=0.5, inside=None, outside=None):
+def spherical_shock_3d(p, x=None, r0=0.5, inside=None, outside=None, width=0.0):
     """3D spherically symmetric shock tube (Example 5.7): the RP1 states of Table 5.1 inside and
     outside the sphere |x| < r0 centred at the origin (v = 0; rho and p are the same in paper
-    and reduced units).  x may be a numpy array or a torch tensor (then the fields are built
-    with the same arithmetic on its device)."""
+    and reduced units).  width > 0 replaces the jump by the profile
+    outside + (inside - outside) (1 - tanh((|x| - r0)/width))/2 (used to adapt an initial mesh).
+    x may be a numpy array or a torch tensor (then the fields are built with the same arithmetic
+    on its device)."""
     x = nodes_xi(p) if x is None else x
     inside = inside or (TABLE_5_1["RP1"][0][0], TABLE_5_1["RP1"][0][2])
     outside = outside or (TABLE_5_1["RP1"][1][0], TABLE_5_1["RP1"][1][2])
     if isinstance(x, np.ndarray):
         r = np.sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2])
         prim = np.zeros((5,) + x[0].shape)
-        prim[0] = np.where(r < r0, inside[0], outside[0])
-        prim[4] = np.where(r < r0, inside[1], outside[1])
+        if width > 0.0:
+            s = 0.5 * (1.0 - np.tanh((r - r0) / width))
+            prim[0] = outside[0] + (inside[0] - outside[0]) * s
+            prim[4] = outside[1] + (inside[1] - outside[1]) * s
+        else:
+            prim[0] = np.where(r < r0, inside[0], outside[0])
+            prim[4] = np.where(r < r0, inside[1], outside[1])
         return np.ascontiguousarray(prim)
     import torch
     r = torch.sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2])
     prim = torch.zeros((5,) + tuple(x.shape[1:]), dtype=torch.float64, device=x.device)
+    if width > 0.0:
+        s = 0.5 * (1.0 - torch.tanh((r - r0) / width))
+        prim[0] = outside[0] + (inside[0] - outside[0]) * s
+        prim[4] = outside[1] + (inside[1] - outside[1]) * s
+        return prim
     # fill, then overwrite inside (torch.where on two Python scalars would round them to FP32)
     inner = r < r0
     prim[0].fill_(outside[0]).masked_fill_(inner, inside[0])
