@@ -96,6 +96,146 @@ __global__ void k_jacobi(Geo G, const double *__restrict__ omega, const double *
   }
 }
 
+// ---- several Jacobi sweeps per launch (2D, outflow walls) ---------------------------------
+// A 64 x 4 block owns a JT_X x JT_Y tile and loads it with a halo of nsw (<= JT_H) nodes into
+// LDS (one extended row per 64-lane row of threads); sweep s updates the extended region shrunk
+// by s, so the owned tile is exact after nsw sweeps.  Nodes outside the domain are never
+// updated: the first ghost layer (the only one a 5-point update reads) is refreshed after every
+// sweep as the mirror image of the wall node (normal coordinate 2 wall - x, tangential x),
+// exactly as mesh_at forms it; omega ghosts are static.  The per-node arithmetic is
+// jacobi_point's, term for term, so the mesh equals nsw launches of k_jacobi bit for bit.
+// Periodic directions are not handled (the launcher falls back to k_jacobi).
+constexpr int JT_X = 54, JT_Y = 10, JT_H = 5;
+constexpr int JT_EX = JT_X + 2 * JT_H, JT_EY = JT_Y + 2 * JT_H, JT_NE = JT_EX * JT_EY;
+static_assert(JT_EX <= 64, "one extended row per 64-lane row of threads");
+
+__global__ void __launch_bounds__(256) k_jacobi_multi2(Geo G, const double *__restrict__ omega,
+                                                       const double *__restrict__ xin, double *__restrict__ xout,
+                                                       int nsw, double *part) {
+  __shared__ double sw[JT_NE], sx[2][2][JT_NE];
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
+  const int exn = JT_X + 2 * nsw, eyn = JT_Y + 2 * nsw;
+  const int gx0 = blockIdx.x * JT_X - nsw, gy0 = blockIdx.y * JT_Y - nsw;
+  const int n0 = G.n[0], n1 = G.n[1];
+  const int gx = gx0 + tx;
+  const bool inner = gx0 >= 0 && gx0 + exn <= n0 && gy0 >= 0 && gy0 + eyn <= n1;  // no ghost in the region
+  if (tx < exn) {
+    if (inner) {
+      for (int ey = ty; ey < eyn; ey += 4) {
+        const int e = ey * exn + tx;
+        const long t = lin(G, gx, gy0 + ey, 0);
+        sw[e] = omega[t];
+        sx[0][0][e] = xin[t];
+        sx[0][1][e] = xin[G.N + t];
+      }
+    } else {
+      for (int ey = ty; ey < eyn; ey += 4) {
+        const int gy = gy0 + ey, e = ey * exn + tx;
+        double w = 0.0, a0 = 0.0, a1 = 0.0;
+        if (gx >= -1 && gx <= n0 && gy >= -1 && gy <= n1) {
+          w = omega[state_index(G, gx, gy, 0)];
+          a0 = mesh_at(G, xin, 0, gx, gy, 0, 0);
+          a1 = mesh_at(G, xin, 1, gx, gy, 0, 0);
+        }
+        sw[e] = w;
+        sx[0][0][e] = a0;
+        sx[0][1][e] = a1;
+      }
+    }
+  }
+  __syncthreads();
+  const double h2x = G.idxi[0] * G.idxi[0], h2y = G.idxi[1] * G.idxi[1];
+  const bool inx = gx >= 0 && gx < n0;
+  // columns / rows of the first ghost layer inside the extended region (-1 if absent)
+  const int cl = gx0 < 0 ? -1 - gx0 : -1, cr = n0 - gx0 < exn ? n0 - gx0 : -1;
+  const int rb = gy0 < 0 ? -1 - gy0 : -1, rt = n1 - gy0 < eyn ? n1 - gy0 : -1;
+  const bool wall = cl >= 0 || cr >= 0 || rb >= 0 || rt >= 0;
+  double r = 0.0;
+  int cur = 0;
+  for (int s = 1; s <= nsw; ++s) {
+    const double *A0 = sx[cur][0], *A1 = sx[cur][1];
+    double *B0 = sx[cur ^ 1][0], *B1 = sx[cur ^ 1][1];
+    if (tx >= s && tx < exn - s && inx)
+      for (int ey = s + ty; ey < eyn - s; ey += 4) {
+        const int gy = gy0 + ey;
+        if (gy < 0 || gy >= n1) continue;
+        const int e = ey * exn + tx;
+        const double w0 = sw[e];
+        double den = 0.0, num0 = 0.0, num1 = 0.0;
+        {  // direction 0, as jacobi_point with k = 0
+          const double wp = 0.5 * (w0 + sw[e + 1]) * h2x;
+          const double wm = 0.5 * (w0 + sw[e - 1]) * h2x;
+          den += wp + wm;
+          num0 += wp * A0[e + 1] + wm * A0[e - 1];
+          num1 += wp * A1[e + 1] + wm * A1[e - 1];
+        }
+        {  // direction 1
+          const double wp = 0.5 * (w0 + sw[e + exn]) * h2y;
+          const double wm = 0.5 * (w0 + sw[e - exn]) * h2y;
+          den += wp + wm;
+          num0 += wp * A0[e + exn] + wm * A0[e - exn];
+          num1 += wp * A1[e + exn] + wm * A1[e - exn];
+        }
+        const double iden = 1.0 / den;
+        const double v0 = num0 * iden, v1 = num1 * iden;
+        if (s == nsw) r = fmax(r, fmax(fabs(v0 - A0[e]), fabs(v1 - A1[e])));
+        B0[e] = v0;
+        B1[e] = v1;
+      }
+    __syncthreads();
+    if (s < nsw && wall) {
+      // ghost columns: for rows of the region inside the domain
+      for (int ey = s + tid; ey < eyn - s; ey += 256) {
+        const int gy = gy0 + ey;
+        if (gy < 0 || gy >= n1) continue;
+        if (cl >= s && cl < exn - s) {
+          const int e = ey * exn + cl;
+          B0[e] = -1.0 * B0[e + 1] + 2.0 * G.lo[0];
+          B1[e] = B1[e + 1];
+        }
+        if (cr >= s && cr < exn - s) {
+          const int e = ey * exn + cr;
+          B0[e] = -1.0 * B0[e - 1] + 2.0 * G.hi[0];
+          B1[e] = B1[e - 1];
+        }
+      }
+      // ghost rows: for columns of the region inside the domain
+      for (int ex = s + tid; ex < exn - s; ex += 256) {
+        const int gxx = gx0 + ex;
+        if (gxx < 0 || gxx >= n0) continue;
+        if (rb >= s && rb < eyn - s) {
+          const int e = rb * exn + ex;
+          B0[e] = B0[e + exn];
+          B1[e] = -1.0 * B1[e + exn] + 2.0 * G.lo[1];
+        }
+        if (rt >= s && rt < eyn - s) {
+          const int e = rt * exn + ex;
+          B0[e] = B0[e - exn];
+          B1[e] = -1.0 * B1[e - exn] + 2.0 * G.hi[1];
+        }
+      }
+      __syncthreads();
+    }
+    cur ^= 1;
+  }
+  if (tx < JT_X) {
+    const int ex = nsw + tx, gxo = gx0 + ex;
+    if (gxo < n0)
+      for (int ey = nsw + ty; ey < nsw + JT_Y; ey += 4) {
+        const int gy = gy0 + ey;
+        if (gy >= n1) continue;
+        const long t = lin(G, gxo, gy, 0);
+        const int e = ey * exn + ex;
+        xout[t] = sx[cur][0][e];
+        xout[G.N + t] = sx[cur][1][e];
+      }
+  }
+  if (part) {
+    double mr = block_max(r);
+    if (flat_tid() == 0) part[flat_bid()] = mr;
+  }
+}
+
 // ---- red-black SOR half-sweep ---------------------------------------------------------
 // Nodes of one colour (i0 + i1 + i2 = colour mod 2), in place.  Thread t of a row takes
 // i0 = 2 t + ((i1 + i2 + colour) & 1).  Each node solves its own equation with the other colour
@@ -251,7 +391,22 @@ static int jacobi_d(esvdw_ctx *c, const double *omega, double *x, int nsweep, do
   node_grid(G.n[0], G.n[1], G.n[2], g, b);
   const long nb = (long)g.x * g.y * g.z;
   double *a = x, *o = c->xtmp;
-  for (int it = 0; it < nsweep; ++it) {
+  const bool multi = D == 2 && G.bc[0] != ESVDW_BC_PERIODIC && G.bc[1] != ESVDW_BC_PERIODIC && nsweep >= 2;
+  if (multi) {
+    const dim3 gm((G.n[0] + JT_X - 1) / JT_X, (G.n[1] + JT_Y - 1) / JT_Y, 1);
+    const long nbm = (long)gm.x * gm.y;  // <= 4 npart
+    for (int done = 0; done < nsweep;) {
+      const int k = nsweep - done < JT_H ? nsweep - done : JT_H;
+      const bool last = done + k == nsweep;
+      hipLaunchKernelGGL(k_jacobi_multi2, gm, dim3(64, 4), 0, st, G, omega, a, o, k, last ? c->part : nullptr);
+      if (last) hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, c->part, nbm, c->scal + SC_RESID, 0);
+      double *tmp = a;
+      a = o;
+      o = tmp;
+      done += k;
+    }
+  }
+  for (int it = 0; !multi && it < nsweep; ++it) {
     bool last = it == nsweep - 1;
     hipLaunchKernelGGL(k_jacobi<D>, g, b, 0, st, G, omega, a, o, last ? c->part : nullptr);
     if (last) hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, c->part, nb, c->scal + SC_RESID, 0);

@@ -108,3 +108,34 @@ def test_sor_solve_beats_jacobi_at_equal_residual(orc, torch_dev):
     assert sweeps_s * 20 < sweeps_j
     assert err_s < err_j
     assert err_s < 1e-6
+
+
+@pytest.mark.parametrize("n,nsweep", [([37, 29], 10), ([1024, 1024], 10), ([100, 7], 7), ([33, 17], 2), ([130, 96], 5)])
+def test_multi_sweep_jacobi_equals_single_sweeps(orc, torch_dev, n, nsweep):
+    """On 2D outflow grids mesh_jacobi runs up to five sweeps per launch from an LDS tile; it must
+    equal nsweep single-sweep calls bit for bit (and the oracle to rounding)."""
+    torch = torch_dev
+    from paper_2407_05568_amd.esvdw import Context
+    p = synth.problem(2, n, bc="outflow")
+    ctx = Context(p)
+    rng = np.random.default_rng(n[0] + nsweep)
+    shape = (n[1], n[0])
+    omega = 1.0 + 3.0 * rng.random(shape)
+    x0 = synth.smooth_mesh(p, 4, amp=0.02)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    om = T(omega)
+    xa, xb = T(x0), T(x0)
+    ra = torch.zeros(1, dtype=torch.float64, device="cuda")
+    rb = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.mesh_jacobi(om, xa, nsweep, ra)
+    for _ in range(nsweep):
+        ctx.mesh_jacobi(om, xb, 1, rb)
+    torch.cuda.synchronize()
+    assert torch.equal(xa, xb)
+    # the residual |v - x| may be formed with or without rounding v first (FMA contraction)
+    assert abs(float(ra.item()) - float(rb.item())) <= 1e-15
+    if n[0] * n[1] <= 20000:
+        o = orc.Oracle(p)
+        xr, _, rr = o.jacobi(omega, x0, nsweep)
+        assert np.abs(xa.cpu().numpy() - xr).max() < 1e-14
+    assert ctx.status() == 0
