@@ -236,6 +236,71 @@ __global__ void __launch_bounds__(256) k_jacobi_multi2(Geo G, const double *__re
   }
 }
 
+// ---- several low-pass filter passes per launch (2D, outflow walls) ---------------------------
+// The tile scheme of k_jacobi_multi2 for the 9-point filter: pass s updates the extended region
+// shrunk by s; the first ghost layer (corners included) is refreshed after every pass with the
+// replicated nearest node, as state_index forms it.  filter_point's arithmetic, term for term.
+__global__ void __launch_bounds__(256) k_filter_multi2(Geo G, const double *__restrict__ in, double *__restrict__ out,
+                                                       int npass) {
+  __shared__ double sa[2][JT_NE];
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
+  const int exn = JT_X + 2 * npass, eyn = JT_Y + 2 * npass;
+  const int gx0 = blockIdx.x * JT_X - npass, gy0 = blockIdx.y * JT_Y - npass;
+  const int n0 = G.n[0], n1 = G.n[1];
+  const int gx = gx0 + tx;
+  if (tx < exn)
+    for (int ey = ty; ey < eyn; ey += 4) {
+      const int gy = gy0 + ey;
+      sa[0][ey * exn + tx] = gx >= -1 && gx <= n0 && gy >= -1 && gy <= n1 ? in[state_index(G, gx, gy, 0)] : 0.0;
+    }
+  __syncthreads();
+  const bool inx = gx >= 0 && gx < n0;
+  const bool wall = gx0 < 0 || gy0 < 0 || gx0 + exn > n0 || gy0 + eyn > n1;
+  int cur = 0;
+  for (int s = 1; s <= npass; ++s) {
+    const double *A = sa[cur];
+    double *B = sa[cur ^ 1];
+    if (tx >= s && tx < exn - s && inx)
+      for (int ey = s + ty; ey < eyn - s; ey += 4) {
+        const int gy = gy0 + ey;
+        if (gy < 0 || gy >= n1) continue;
+        const int e = ey * exn + tx;
+        double v = 0.0;
+#pragma unroll
+        for (int j1 = -1; j1 <= 1; ++j1)
+#pragma unroll
+          for (int j0 = -1; j0 <= 1; ++j0) {
+            int l1 = (j0 != 0) + (j1 != 0) + 2;
+            v += ldexp(1.0, -l1) * A[e + j1 * exn + j0];
+          }
+        B[e] = v;
+      }
+    __syncthreads();
+    if (s < npass && wall) {
+      // first ghost layer inside the region: the nearest node's value
+      if (tx >= s && tx < exn - s)
+        for (int ey = s + ty; ey < eyn - s; ey += 4) {
+          const int gy = gy0 + ey;
+          const bool iny = gy >= 0 && gy < n1;
+          if (inx && iny) continue;
+          if (gx < -1 || gx > n0 || gy < -1 || gy > n1) continue;
+          const int sx = gx < 0 ? 0 : (gx >= n0 ? n0 - 1 : gx), sy = gy < 0 ? 0 : (gy >= n1 ? n1 - 1 : gy);
+          B[ey * exn + tx] = B[(sy - gy0) * exn + (sx - gx0)];
+        }
+      __syncthreads();
+    }
+    cur ^= 1;
+  }
+  if (tx < JT_X) {
+    const int ex = npass + tx, gxo = gx0 + ex;
+    if (gxo < n0)
+      for (int ey = npass + ty; ey < npass + JT_Y; ey += 4) {
+        const int gy = gy0 + ey;
+        if (gy < n1) out[lin(G, gxo, gy, 0)] = sa[cur][ey * exn + ex];
+      }
+  }
+}
+
 // ---- red-black SOR half-sweep ---------------------------------------------------------
 // Nodes of one colour (i0 + i1 + i2 = colour mod 2), in place.  Thread t of a row takes
 // i0 = 2 t + ((i1 + i2 + colour) & 1).  Each node solves its own equation with the other colour
@@ -363,15 +428,22 @@ template <int D> static int monitor_d(esvdw_ctx *c, const double *JU, const doub
                      c->mterm, c->part, c->npart);
   for (int q = 0; q < nterm; ++q)
     hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, c->part + q * c->npart, nb, c->scal + SC_MON + q, 0);
-  // filtered result must end in `omega`: start in omega2 when the pass count is odd
-  double *cur = (p.n_filter % 2) ? c->omega2 : omega;
-  double *oth = (p.n_filter % 2) ? omega : c->omega2;
+  // 2D outflow grids run up to JT_H passes per launch; the filtered result must end in `omega`:
+  // start in omega2 when the launch count is odd
+  const bool multi = D == 2 && G.bc[0] != ESVDW_BC_PERIODIC && G.bc[1] != ESVDW_BC_PERIODIC && p.n_filter >= 2;
+  const int nlaunch = multi ? (p.n_filter + JT_H - 1) / JT_H : p.n_filter;
+  double *cur = (nlaunch % 2) ? c->omega2 : omega;
+  double *oth = (nlaunch % 2) ? omega : c->omega2;
   hipLaunchKernelGGL(k_mon_omega, g, b, 0, st, G, nterm, p.alpha[0], p.alpha[1], p.alpha[2], c->mterm, c->scal, cur);
-  for (int i = 0; i < p.n_filter; ++i) {
-    hipLaunchKernelGGL(k_filter<D>, g, b, 0, st, G, cur, oth);
+  const dim3 gm((G.n[0] + JT_X - 1) / JT_X, (G.n[1] + JT_Y - 1) / JT_Y, 1);
+  for (int done = 0; done < p.n_filter;) {
+    const int k = multi ? (p.n_filter - done < JT_H ? p.n_filter - done : JT_H) : 1;
+    if (multi) hipLaunchKernelGGL(k_filter_multi2, gm, dim3(64, 4), 0, st, G, cur, oth, k);
+    else hipLaunchKernelGGL(k_filter<D>, g, b, 0, st, G, cur, oth);
     double *tmp = cur;
     cur = oth;
     oth = tmp;
+    done += k;
   }
   return CHK();
 }

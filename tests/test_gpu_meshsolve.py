@@ -139,3 +139,26 @@ def test_multi_sweep_jacobi_equals_single_sweeps(orc, torch_dev, n, nsweep):
         xr, _, rr = o.jacobi(omega, x0, nsweep)
         assert np.abs(xa.cpu().numpy() - xr).max() < 1e-14
     assert ctx.status() == 0
+
+
+@pytest.mark.parametrize("n,nf", [([37, 29], 5), ([120, 30], 7), ([55, 13], 20), ([6, 6], 2), ([300, 200], 5)])
+def test_multi_pass_filter_matches_oracle(orc, torch_dev, n, nf):
+    """On 2D outflow grids the monitor's low-pass filter runs up to five passes per launch; the
+    filtered monitor must equal the oracle's (the one its redistribution uses) to rounding."""
+    torch = torch_dev
+    from paper_2407_05568_amd.esvdw import Context
+    p = synth.problem(2, n, bc="outflow", n_filter=nf)
+    o = orc.Oracle(p)
+    x = synth.smooth_mesh(p, 2, amp=0.02)
+    J = o.jacobian(x)
+    JU = o.init_state(synth.quadrants_2d(p, synth.quadrant_states(p, 2)), J)
+    want = o.redistribute(JU, J, x)["omega"]
+    ctx = Context(p)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    om = torch.empty(o.shape, dtype=torch.float64, device="cuda")
+    ctx.mesh_monitor(T(JU), T(J), om)
+    torch.cuda.synchronize()
+    err = np.abs(om.cpu().numpy() - want).max() / np.abs(want).max()
+    print("%s n_filter %d: omega rel err %.2e" % (n, nf, err))
+    assert err < 1e-14
+    assert ctx.status() == 0
