@@ -46,6 +46,11 @@ extern "C" {
 
 #define ESVDW_BC_PERIODIC 0
 #define ESVDW_BC_OUTFLOW 1 /* state: zero gradient; mesh: mirror about the boundary face */
+/* esvdw_params.walls bits: a face of an outflow direction k may instead be a reflecting (slip)
+ * wall (Examples 5.4-5.5 have walls): state ghosts mirror the interior about the face with the
+ * velocity component normal to it reversed; the mesh mirrors as for outflow. */
+#define ESVDW_WALL_LO(k) (1 << (2 * (k)))
+#define ESVDW_WALL_HI(k) (1 << (2 * (k) + 1))
 
 #define ESVDW_MON_VDW 0  /* monitor of Section 4 (squared gradient terms + |Delta G|^2) */
 #define ESVDW_MON_SINE 1 /* monitor of Example 5.1 (|grad rho|, |Delta rho|) */
@@ -71,6 +76,7 @@ typedef struct esvdw_params {
   int mu;               /* Jacobi sweeps (fixed mode) or the sweep cap (tolerance mode) */
   double mesh_tol;      /* tolerance of the Jacobi stop test (max node update) */
   int fixed_mu;         /* 1: exactly mu sweeps; 0: stop once the update is < mesh_tol */
+  int walls;            /* ESVDW_WALL_LO / _HI bits (outflow directions only; 0: none) */
 } esvdw_params;
 
 typedef struct esvdw_ctx esvdw_ctx;

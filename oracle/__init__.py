@@ -44,7 +44,7 @@ class Cfg(ctypes.Structure):
         ("cfl", ctypes.c_double), ("dt_fixed", ctypes.c_double),
         ("monitor_kind", ctypes.c_int), ("kappa", ctypes.c_int), ("mon_var", ctypes.c_int * 2),
         ("alpha", ctypes.c_double * 3), ("n_filter", ctypes.c_int), ("mu", ctypes.c_int),
-        ("mesh_tol", ctypes.c_double), ("fixed_mu", ctypes.c_int),
+        ("mesh_tol", ctypes.c_double), ("fixed_mu", ctypes.c_int), ("walls", ctypes.c_int),
     ]
 
 
@@ -76,6 +76,12 @@ def make_cfg(p):
     c.mu = int(p["mu"])
     c.mesh_tol = float(p["mesh_tol"])
     c.fixed_mu = int(p["fixed_mu"])
+    walls = 0
+    for k, side in p.get("walls", ()):
+        if BC[p["bc"][int(k)]] != BC["outflow"]:
+            raise ValueError("walls are faces of outflow directions")
+        walls |= 1 << (2 * int(k) + (1 if side == "hi" else 0))
+    c.walls = walls
     return c
 
 

@@ -55,6 +55,7 @@ typedef struct {
   int mu;                   /* Jacobi sweeps (fixed), or the cap in tolerance mode */
   double mesh_tol;
   int fixed_mu;             /* 1: exactly mu sweeps; 0: stop when the update < tol */
+  int walls;                /* bit 2k: the lo face of direction k is a reflecting wall; 2k+1: hi */
 } orc_cfg;
 
 static unsigned g_flags = 0;
@@ -482,11 +483,13 @@ static long iidx(const orc_cfg *c, int i0, int i1, int i2) {
 static double dxi(const orc_cfg *c, int k) { return (c->hi[k] - c->lo[k]) / c->n[k]; }
 
 /* Fill the ghost layers of nf padded scalar fields, direction by direction.
- * kind 0: scalar copy (periodic wrap, outflow: nearest interior node).
+ * kind 0: state field (periodic wrap, outflow: nearest interior node; reflecting wall face:
+ *         mirror image, sign reversed when the field is the momentum component `coord` == k;
+ *         coord = -1 for fields that are not momentum components).
  * kind 1: mesh coordinate field number `coord` (periodic: shift by one period when
- *         coord == k; outflow: mirror about the boundary face, odd in coord == k).
+ *         coord == k; outflow and walls: mirror about the boundary face, odd in coord == k).
  * kind 2: mesh velocity component `coord` (periodic: plain wrap; outflow: mirror, odd).
- * kind 3: scalar replicate/wrap (same as 0; used for the monitor). */
+ * kind 3: scalar replicate/wrap, mirror at a wall face (used for the monitor). */
 static void fill_ghosts(const orc_cfg *c, const pad_t *p, double *f, int kind, int coord) {
   for (int k = 0; k < c->dim; ++k) {
     int n = p->n[k], g = p->g[k];
@@ -510,7 +513,12 @@ static void fill_ghosts(const orc_cfg *c, const pad_t *p, double *f, int kind, i
                 is = side == 0 ? ig + n : ig - n;
                 if (kind == 1 && coord == k) shift = side == 0 ? -(c->hi[k] - c->lo[k]) : (c->hi[k] - c->lo[k]);
               } else {
-                if (kind == 0 || kind == 3) {
+                int wall = (c->walls >> (2 * k + side)) & 1;
+                if ((kind == 0 || kind == 3) && wall) {
+                  /* reflecting wall: mirror image, normal momentum reversed */
+                  is = side == 0 ? -1 - ig : 2 * n - 1 - ig;
+                  if (kind == 0 && coord == k) sgn = -1.0;
+                } else if (kind == 0 || kind == 3) {
                   is = side == 0 ? 0 : n - 1;
                 } else {
                   is = side == 0 ? -1 - ig : 2 * n - 1 - ig;
@@ -873,7 +881,7 @@ static double **pad_state(const orc_cfg *c, const pad_t *pm, const double *JU, c
           long qi = iidx(c, i0, i1, i2);
           Up[v][pidx(pm, i0, i1, i2)] = JU[v * N + qi] / J[qi];
         }
-    fill_ghosts(c, pm, Up[v], 0, 0);
+    fill_ghosts(c, pm, Up[v], 0, v >= 1 && v <= d ? v - 1 : -1);
   }
   return Up;
 }
@@ -1067,8 +1075,8 @@ void orc_monitor(const orc_cfg *c, const double *JU, const double *J, double *om
   }
   to_pad(c, &p1, rhoi, rho);
   to_pad(c, &p1, Gi, G);
-  fill_ghosts(c, &p1, rho, 0, 0);
-  fill_ghosts(c, &p1, G, 0, 0);
+  fill_ghosts(c, &p1, rho, 0, -1);
+  fill_ghosts(c, &p1, G, 0, -1);
   int nterm = c->monitor_kind == MON_VDW ? c->kappa + 1 : 2;
   double *term = calloc((long)nterm * N, sizeof(double));
   double mxv[3] = {0, 0, 0};

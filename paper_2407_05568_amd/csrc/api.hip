@@ -14,7 +14,9 @@ int params_valid(const esvdw_params *p) {
     if (p->n[k] < 6) return 0;
     if (!(p->hi[k] > p->lo[k])) return 0;
     if (p->bc[k] != ESVDW_BC_PERIODIC && p->bc[k] != ESVDW_BC_OUTFLOW) return 0;
+    if (p->bc[k] == ESVDW_BC_PERIODIC && (p->walls & (ESVDW_WALL_LO(k) | ESVDW_WALL_HI(k)))) return 0;
   }
+  if (p->walls < 0 || (p->walls >> (2 * p->dim)) != 0) return 0;
   if (!(p->R > 0.0) || !(p->cv > 0.0) || p->a < 0.0 || p->b < 0.0) return 0;
   if (!(p->weno_lin[0] > 0.0) || p->weno_lin[1] < 0.0 || p->weno_lin[2] < 0.0 || !(p->weno_eps > 0.0)) return 0;
   if (!(p->cfl > 0.0) && !(p->dt_fixed > 0.0)) return 0;
@@ -44,6 +46,7 @@ void make_geo(const esvdw_params *p, Geo *G) {
     G->idxi[k] = 1.0 / G->dxi[k];
     G->period[k] = G->hi[k] - G->lo[k];
     G->bc[k] = act ? p->bc[k] : ESVDW_BC_PERIODIC;
+    G->walls = p->walls;
     G->N *= G->n[k];
     G->PN *= G->P[k];
   }

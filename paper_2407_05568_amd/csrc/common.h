@@ -21,6 +21,7 @@ struct Geo {
   long N, PN;  // interior / padded node counts
   double lo[3], hi[3], dxi[3], idxi[3], period[3];
   int bc[3];
+  int walls;  // ESVDW_WALL_* bits
   double R, cv, a, b, delta, iR;
   double wl0, wl1, wl2, weps, iwl0;
   int diss;
@@ -33,11 +34,13 @@ struct Geo {
 
 __device__ __forceinline__ int floordiv(int i, int n) { return i >= 0 ? i / n : -((-i + n - 1) / n); }
 
-// interior source of a (possibly ghost) state index along one direction
-__device__ __forceinline__ int state_src(int i, int n, int bc) {
+// interior source of a (possibly ghost) state index along direction k: periodic wrap, mirror
+// at a wall face, else the nearest node
+__device__ __forceinline__ int state_src(int i, int n, int bc, int walls, int k) {
   if (i >= 0 && i < n) return i;
   if (bc == ESVDW_BC_PERIODIC) return i - floordiv(i, n) * n;
-  return i < 0 ? 0 : n - 1;
+  if (i < 0) return (walls & ESVDW_WALL_LO(k)) ? -1 - i : 0;
+  return (walls & ESVDW_WALL_HI(k)) ? 2 * n - 1 - i : n - 1;
 }
 
 __device__ __forceinline__ long lin(const Geo &G, int i0, int i1, int i2) {
@@ -47,7 +50,8 @@ __device__ __forceinline__ long lin(const Geo &G, int i0, int i1, int i2) {
 __device__ __forceinline__ long state_index(const Geo &G, int i0, int i1, int i2) {
   if ((unsigned)i0 < (unsigned)G.n[0] && (unsigned)i1 < (unsigned)G.n[1] && (unsigned)i2 < (unsigned)G.n[2])
     return lin(G, i0, i1, i2);
-  return lin(G, state_src(i0, G.n[0], G.bc[0]), state_src(i1, G.n[1], G.bc[1]), state_src(i2, G.n[2], G.bc[2]));
+  return lin(G, state_src(i0, G.n[0], G.bc[0], G.walls, 0), state_src(i1, G.n[1], G.bc[1], G.walls, 1),
+             state_src(i2, G.n[2], G.bc[2], G.walls, 2));
 }
 
 // Mesh coordinate j at any index within the ghost reach: periodic directions wrap with a

@@ -48,6 +48,13 @@ __device__ __forceinline__ void node_point(const Geo &G, const double *__restric
     v[m] = JU[(long)(1 + m) * G.N + s] * iJ * irho;
     v2 += v[m] * v[m];
   }
+  if (G.walls) {  // a ghost beyond a wall face carries the mirrored velocity
+    const int ii[3] = {i0, i1, i2};
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+      if ((ii[q] < 0 && (G.walls & ESVDW_WALL_LO(q))) || (ii[q] >= G.n[q] && (G.walls & ESVDW_WALL_HI(q))))
+        v[q] = -v[q];
+  }
   double e = JU[(long)(D + 1) * G.N + s] * iJ * irho - 0.5 * v2;
   double T = (e + G.a * rho) / G.cv;
   double iT = 1.0 / T;

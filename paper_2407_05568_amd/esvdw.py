@@ -36,7 +36,7 @@ class Params(ctypes.Structure):
         ("cfl", ctypes.c_double), ("dt_fixed", ctypes.c_double),
         ("monitor_kind", ctypes.c_int), ("kappa", ctypes.c_int), ("mon_var", ctypes.c_int * 2),
         ("alpha", ctypes.c_double * 3), ("n_filter", ctypes.c_int), ("mu", ctypes.c_int),
-        ("mesh_tol", ctypes.c_double), ("fixed_mu", ctypes.c_int),
+        ("mesh_tol", ctypes.c_double), ("fixed_mu", ctypes.c_int), ("walls", ctypes.c_int),
     ]
 
 
@@ -66,6 +66,8 @@ def params_from(p):
     c.mu = int(p["mu"])
     c.mesh_tol = float(p["mesh_tol"])
     c.fixed_mu = int(p["fixed_mu"])
+    # reflecting walls: (direction, "lo" | "hi") faces of outflow directions
+    c.walls = sum(1 << (2 * int(k) + (side == "hi")) for k, side in p.get("walls", ()))
     return c
 
 
