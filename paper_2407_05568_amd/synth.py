@@ -364,6 +364,34 @@ def spherical_shock_3d(p, x=None, r0=0.5, inside=None, outside=None, width=0.0):
     return prim
 
 
+# Table 5.3 of the paper (Example 5.4): gamma, (rho, v1, v2, p) behind and ahead of the shock;
+# velocities in the paper's unit (reduced velocities are sqrt(8/3) times larger), incidence
+# angle theta (degrees) and shock Mach number as printed
+TABLE_5_3 = {
+    "P1": dict(gamma=1.4, left=(0.033, 5.016, 0.0, 3.001), right=(0.0156, 0.0, 0.0, 1.0), theta=20.0, mach=1.65),
+    "D1": dict(gamma=1.0125, left=(0.629, -0.135, 0.0, 0.983), right=(0.879, 0.0, 0.0, 1.09), theta=30.0, mach=1.05),
+}
+
+
+def mach_reflection(p, case, x=None, foot=0.1):
+    """Example 5.4's oblique shock in reduced units: a planar shock whose normal points along
+    (cos theta, -sin theta) toward the wall x_2 = 0, its foot on the wall at x_1 = foot; behind it
+    the state `left` of Table 5.3 moving along that normal with speed |v1| sqrt(8/3) (signed as
+    printed), ahead of it the state `right` at rest."""
+    c = TABLE_5_3[case]
+    x = nodes_xi(p) if x is None else x
+    th = math.radians(c["theta"])
+    n0, n1 = math.cos(th), -math.sin(th)
+    behind = (x[0] - foot) * n0 + x[1] * n1 < 0.0
+    u = c["left"][1] * math.sqrt(8.0 / 3.0)
+    prim = np.zeros((4,) + x[0].shape)
+    prim[0] = np.where(behind, c["left"][0], c["right"][0])
+    prim[1] = np.where(behind, u * n0, 0.0)
+    prim[2] = np.where(behind, u * n1, 0.0)
+    prim[3] = np.where(behind, c["left"][3], c["right"][3])
+    return np.ascontiguousarray(prim)
+
+
 def batch_instances(seed, count=256, nmin=64, nmax=384):
     """Independent 2D Riemann instances: n ~ U{nmin..nmax} (square grids), a ~ U[2, 4],
     b ~ U[0.2, 0.4], R = 8/3, c_v = R/0.0125; quadrant states drawn in reduced form and
