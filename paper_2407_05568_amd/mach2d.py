@@ -24,7 +24,7 @@ import time
 
 import numpy as np
 
-from . import synth
+from . import runner, synth
 from .esvdw import Context
 
 FOOT, TRAVEL = 0.1, 0.6
@@ -52,33 +52,15 @@ def run(torch, case, n0, n1, moving=True, alpha2=500.0, log=None):
     x = torch.empty((2, n1, n0), **f64)
     J = torch.empty((n1, n0), **f64)
     JU = torch.empty((4, n1, n0), **f64)
-    dt = torch.zeros(1, **f64)
     st = torch.cuda.current_stream()
     ctx.init_mesh(x, J, 1, st)
     ctx.init_state(torch.from_numpy(synth.mach_reflection(p, case, foot=FOOT)).cuda(), J, JU, st)
     te = t_end(case)
-    t, steps, gpu_ms, last_dt, cur, tail = 0.0, 0, 0.0, 0.0, ctx, None
-    while t < te * (1.0 - 1e-14):
-        if tail is None and last_dt > 0.0 and te - t < 2.0 * last_dt:
-            # land on the final time: the remaining time in two equal fixed steps
-            tail = Context(dict(p, dt_fixed=0.5 * (te - t)))
-            cur = tail
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(st)
-        cur.step(JU, J, x, 1 if moving else 0, dt, st)
-        e1.record(st)
-        torch.cuda.synchronize()
-        gpu_ms += e0.elapsed_time(e1)
-        last_dt = float(dt.item())
-        t += last_dt
-        steps += 1
-        if log and steps % 500 == 0:
-            log("%s %dx%d: step %d t %.4f / %.4f" % (case, n0, n1, steps, t, te))
-    flags = ctx.status() | (tail.status() if tail is not None else 0)
+    r = runner.advance_to(torch, ctx, p, JU, J, x, moving, te, log=log)
     rho = (JU[0] / J).cpu().numpy()
-    return dict(case=case, n=[n0, n1], moving=moving, alpha2=alpha2, steps=steps, t=t, t_end=te, gpu_ms=gpu_ms,
-                ms_per_step=gpu_ms / max(steps, 1), flags=flags, min_J=float(J.min())), rho, x.cpu().numpy(), \
-        J.cpu().numpy()
+    return dict(case=case, n=[n0, n1], moving=moving, alpha2=alpha2, steps=r["steps"], t=r["t"], t_end=te,
+                gpu_ms=r["gpu_ms"], ms_per_step=r["gpu_ms"] / max(r["steps"], 1), graph_steps=r["graph_steps"],
+                flags=r["flags"], min_J=float(J.min())), rho, x.cpu().numpy(), J.cpu().numpy()
 
 
 def l1_error(rho, x, J, ref, dxi_area):

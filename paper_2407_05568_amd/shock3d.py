@@ -31,7 +31,7 @@ import time
 
 import numpy as np
 
-from . import synth
+from . import runner, synth
 from .esvdw import Context
 
 T_END = 0.2 * math.sqrt(3.0 / 8.0)
@@ -71,14 +71,13 @@ def preadapt(torch, ctx, p, x, J, JU, passes, tol=0.1, theta=0.5, stream=None):
     return done, move
 
 
-def run(torch, n, t_end=T_END, moving=True, max_steps=100000, passes=400, log=None):
+def run(torch, n, t_end=T_END, moving=True, passes=400, log=None):
     p = problem(n)
     ctx = Context(p)
     f64 = dict(dtype=torch.float64, device="cuda")
     x = torch.empty((3, n, n, n), **f64)
     J = torch.empty((n, n, n), **f64)
     JU = torch.empty((5, n, n, n), **f64)
-    dt = torch.zeros(1, **f64)
     st = torch.cuda.current_stream()
     ctx.init_mesh(x, J, 1, st)
     ctx.init_state(synth.spherical_shock_3d(p, x), J, JU, st)
@@ -94,27 +93,10 @@ def run(torch, n, t_end=T_END, moving=True, max_steps=100000, passes=400, log=No
         if log:
             log("initial mesh: %d passes, last move %.3f cells, %.1f ms" % (pre[0], pre[1], pre_ms))
     mass0 = float(JU[0].sum())
-    t, steps, gpu_ms = 0.0, 0, 0.0
     w0 = time.perf_counter()
-    cur, last_dt, tail = ctx, 0.0, None
-    while t < t_end * (1.0 - 1e-14) and steps < max_steps:
-        if tail is None and last_dt > 0.0 and t_end - t < 2.0 * last_dt:
-            # land on t_end: the remaining time in two equal fixed steps (each below the last CFL step)
-            tail = Context(dict(p, dt_fixed=0.5 * (t_end - t)))
-            cur = tail
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(st)
-        cur.step(JU, J, x, 1 if moving else 0, dt, st)
-        e1.record(st)
-        torch.cuda.synchronize()
-        gpu_ms += e0.elapsed_time(e1)
-        last_dt = float(dt.item())
-        t += last_dt
-        steps += 1
-        if log and steps % 10 == 0:
-            log("step %d t %.4f (%.1f ms per step)" % (steps, t, gpu_ms / steps))
+    r = runner.advance_to(torch, ctx, p, JU, J, x, moving, t_end, block=10, log=log)
     wall = time.perf_counter() - w0
-    flags = ctx.status() | (tail.status() if tail is not None else 0)
+    t, steps, gpu_ms, flags = r["t"], r["steps"], r["gpu_ms"], r["flags"]
     U = (JU / J).cpu().numpy()
     rho = U[0]
     # symmetries of the data: the mirrors x_k -> -x_k are kept by the scheme up to rounding
@@ -128,7 +110,7 @@ def run(torch, n, t_end=T_END, moving=True, max_steps=100000, passes=400, log=No
     xs = x.cpu().numpy()
     diag = [(float(np.sqrt(3.0) * xs[0, i, i, i]), float(rho[i, i, i])) for i in range(h, n)]
     return dict(size=n, moving=moving, preadapt_passes=pre[0], preadapt_last_move=pre[1], preadapt_ms=pre_ms,
-                min_J=float(J.min()), steps=steps, t=t, t_end=t_end, gpu_ms=gpu_ms, wall_s=wall, ms_per_step=gpu_ms / max(steps, 1),
+                min_J=float(J.min()), steps=steps, graph_steps=r["graph_steps"], t=t, t_end=t_end, gpu_ms=gpu_ms, wall_s=wall, ms_per_step=gpu_ms / max(steps, 1),
                 mass_drift=(float(JU[0].sum()) - mass0) / mass0, mirror_err=float(mirror), permutation_err=float(perm), flags=flags,
                 rho_min=float(rho.min()), rho_max=float(rho.max()), diagonal=diag)
 
