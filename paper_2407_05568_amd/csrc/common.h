@@ -125,7 +125,7 @@ __device__ __forceinline__ double metric_at(const Geo &G, const double *xn, cons
     return sg * delta_x(G, xn, xd, cdt, kk, jj, i0, i1, i2) * G.idxi[kk];
   }
   // D == 3: (delta_{k2}[delta_{k1}[x_{j1}] x_{j2}] - delta_{k1}[delta_{k2}[x_{j1}] x_{j2}]) / (dxi_{k1} dxi_{k2})
-  int k1 = (k + 1) % 3, k2 = (k + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+  int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
   const double al[3] = {AL1, AL2, AL3};
   double s = 0.0;
   for (int term = 0; term < 2; ++term) {
@@ -136,8 +136,9 @@ __device__ __forceinline__ double metric_at(const Geo &G, const double *xn, cons
     for (int m = 1; m <= 3; ++m) {
       int a0 = i0 + m * e[0], a1 = i1 + m * e[1], a2 = i2 + m * e[2];
       int b0 = i0 - m * e[0], b1 = i1 - m * e[1], b2 = i2 - m * e[2];
-      double fa = dp[(long)(in * 3 + j1) * dpN + dp_index(G, a0, a1, a2)] * stage_x(G, xn, xd, cdt, j2, a0, a1, a2);
-      double fb = dp[(long)(in * 3 + j1) * dpN + dp_index(G, b0, b1, b2)] * stage_x(G, xn, xd, cdt, j2, b0, b1, b2);
+      // dp holds delta_in[x_{j+1}] x_{j+2} at every padded node
+      double fa = dp[(long)(in * 3 + j) * dpN + dp_index(G, a0, a1, a2)];
+      double fb = dp[(long)(in * 3 + j) * dpN + dp_index(G, b0, b1, b2)];
       acc += al[m - 1] * (fa - fb);
     }
     s += (term == 0 ? 0.5 : -0.5) * acc;
@@ -415,7 +416,7 @@ struct esvdw_ctx {
   double *node_mem;  // the allocation behind node
   double *flux[3];   // per direction: (nv + 1) * interfaces
   long nif[3];       // interfaces per direction
-  double *dprod;     // 3D: 9 fields of delta_q[x_r] on a 6-ghost padded grid
+  double *dprod;     // 3D: 9 fields of delta_q[x_{j+1}] x_{j+2} on a 6-ghost padded grid
   long dpN;          // padded node count of dprod
   double *met;       // dim*dim + dim fields (interior), scratch for cfl/jacobian
   double *stA, *stB; // RK stage buffers, (nv + 1) * N each

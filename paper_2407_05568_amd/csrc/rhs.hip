@@ -1,6 +1,6 @@
 // rhs.hip -- metrics, node thermodynamics, interface fluxes and the RK-stage update of the
 // entropy-stable moving-mesh scheme (Sections 3.1-3.3).  One launch pipeline per RHS:
-//   k_dprod (3D only)  delta_q[x_r] on the stage mesh
+//   k_dprod (3D only)  delta_q[x_r] x_s products on the stage mesh
 //   k_nodes            per padded node: primitives, 1/T, g, entropy variables, metrics
 //   k_flux<K>          per interface along K: sixth-order EC flux + MR-WENO dissipation
 //   k_update           flux differences, optional SSP-RK3 combination
@@ -10,8 +10,9 @@
 
 // =============================== metrics ========================================
 
-// 3D: dprod[q*3 + r] = delta_q[x_r] on a grid padded by 6 in every direction (valid where
-// the q index is within 3 of the interior, which is where it is used)
+// 3D: dprod[q*3 + j] = delta_q[x_{j+1}] x_{j+2} (indices mod 3), the inner products of the
+// nested metric form, on a grid padded by 6 in every direction (valid where the q index is
+// within 3 of the interior, which is where it is used)
 __global__ void k_dprod(Geo G, const double *__restrict__ xn, const double *__restrict__ xd, double cdt,
                         double *__restrict__ dp, long dpN) {
   const int P0 = G.n[0] + 12, P1 = G.n[1] + 12;
@@ -22,9 +23,13 @@ __global__ void k_dprod(Geo G, const double *__restrict__ xn, const double *__re
   const int i0 = (int)(blockIdx.x * blockDim.x + threadIdx.x) - 6,
             i1 = (int)(blockIdx.y * blockDim.y + threadIdx.y) - 6, i2 = (int)blockIdx.z - 6;
   int ii[3] = {i0, i1, i2};
+  const double xs[3] = {stage_x(G, xn, xd, cdt, 0, i0, i1, i2), stage_x(G, xn, xd, cdt, 1, i0, i1, i2),
+                        stage_x(G, xn, xd, cdt, 2, i0, i1, i2)};
   for (int q = 0; q < 3; ++q) {
     bool ok = ii[q] >= -3 && ii[q] < G.n[q] + 3;
-    for (int r = 0; r < 3; ++r) dp[(long)(q * 3 + r) * dpN + t] = ok ? delta_x(G, xn, xd, cdt, q, r, i0, i1, i2) : 0.0;
+    for (int j = 0; j < 3; ++j)
+      dp[(long)(q * 3 + j) * dpN + t] =
+          ok ? delta_x(G, xn, xd, cdt, q, (j + 1) % 3, i0, i1, i2) * xs[(j + 2) % 3] : 0.0;
   }
   }
 }
