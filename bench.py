@@ -16,7 +16,6 @@ Prints one JSON line.  value = node-stages per second = nodes * 3 * steps / time
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -119,8 +118,8 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the path shards by spatial domain "
-              "decomposition, see the design notes); run with --gpus 1", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU (several would split the grid into slabs with halo "
+              "exchanges, which is not implemented); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -12,7 +12,7 @@
  * dimensionless units are (R, c_v, a, b) = (1, 1/delta, 9/8, 1/3), where p equals
  * 3/8 of the dimensionless p_* (Section 2).
  *
- * Readings where the paper is silent (all documented in the design notes):
+ * Readings where the paper is silent:
  *  - nodes are cell-centred, xi_i = lo + (i + 1/2) dxi;
  *  - ghost states copy the nearest interior node (outflow) or wrap (periodic);
  *    ghost mesh nodes mirror about the boundary face (normal coordinate odd,

@@ -1,7 +1,6 @@
 """Build the gfx950 HIP library libesvdw.so in-tree with hipcc."""
 import os
 import subprocess
-import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")

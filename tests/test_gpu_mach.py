@@ -3,7 +3,6 @@ mesh, run to the final time at 64 x 32: no status flags, the final time reached 
 density inside the range the two states and the reflection allow, and mass changed only
 through the open faces (the wall keeps none from leaving: the change stays far below the mass
 the open faces could carry)."""
-import numpy as np
 import pytest
 
 from paper_2407_05568_amd import mach2d, synth

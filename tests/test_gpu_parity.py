@@ -7,7 +7,6 @@ nonlinear MR-WENO weights amplify rounding of W (whose c_v ln T terms are large 
 delta = 0.0125), so each test first measures the oracle's own sensitivity kappa (the
 relative output change when every input is perturbed by one unit in the last place) and
 uses tol = max(1e-12, 8 kappa) (per call) or max(1e-9, 8 kappa) (100 steps)."""
-import math
 
 import numpy as np
 import pytest
