@@ -282,6 +282,38 @@ def test_free_stream_full_size(torch_dev):
     assert ctx.status() == 0
 
 
+def test_free_stream_full_size_3d(torch_dev):
+    """Remark 3.4 at the 3D benchmark size (192^3, the nested metric form of eq. SCLCoeff): a
+    uniform state on a moving periodic mesh stays uniform to round-off over 2 GPU steps."""
+    torch = torch_dev
+    from paper_2407_05568_amd.esvdw import Context
+    n = 192
+    p = synth.problem(3, [n, n, n], bc="periodic")
+    ctx = Context(p)
+    x = synth.smooth_mesh(p, 4, amp=0.02)
+    xd = synth.smooth_velocity(p, 5, amp=0.2)
+    xg, xdg = T(torch, x), T(torch, xd)
+    del x, xd
+    Jg = torch.empty((n, n, n), dtype=torch.float64, device="cuda")
+    ctx.init_mesh(xg, Jg, 0)
+    prim = synth.uniform_state(p)
+    JUg = torch.empty((5, n, n, n), dtype=torch.float64, device="cuda")
+    ctx.init_state(T(torch, prim), Jg, JUg)
+    U0 = (JUg[:, 0, 0, 0] / Jg[0, 0, 0]).clone()
+    dtg = T(torch, np.array([1e-4]))
+    A = torch.empty_like(JUg), torch.empty_like(Jg)
+    B = torch.empty_like(JUg), torch.empty_like(Jg)
+    for _ in range(2):
+        ctx.rk_stage(0, dtg, JUg, Jg, JUg, Jg, xg, xdg, A[0], A[1])
+        ctx.rk_stage(1, dtg, JUg, Jg, A[0], A[1], xg, xdg, B[0], B[1])
+        ctx.rk_stage(2, dtg, JUg, Jg, B[0], B[1], xg, xdg, JUg, Jg, xg)
+    U = JUg / Jg[None]
+    dev = (U - U0[:, None, None, None]).abs().amax(dim=(1, 2, 3)) / U0.abs().clamp(min=1.0)
+    print("192^3 free stream: max deviation %.2e" % float(dev.max()))
+    assert float(dev.max()) < 1e-13
+    assert ctx.status() == 0
+
+
 def test_inadmissible_flag(torch_dev):
     torch = torch_dev
     from paper_2407_05568_amd.esvdw import Context
