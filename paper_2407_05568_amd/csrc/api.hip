@@ -281,10 +281,21 @@ int esvdw_step(esvdw_ctx *c, double *JU, double *J, double *x, int moving, doubl
     return ESVDW_EHIP;
   }
   double *aU = c->stA, *aJ = c->stA + (long)nv * N, *bU = c->stB, *bJ = c->stB + (long)nv * N;
-  int r = rk_stage(c, 0, dt_dev, JU, J, JU, J, x, xd, aU, aJ, nullptr, st);
-  if (!r) r = rk_stage(c, 1, dt_dev, JU, J, aU, aJ, x, xd, bU, bJ, nullptr, st);
-  if (!r) r = rk_stage(c, 2, dt_dev, JU, J, bU, bJ, x, xd, JU, J, moving ? x : nullptr, st);
-  return r;
+  if (!xd) {
+    int r = rk_stage(c, 0, dt_dev, JU, J, JU, J, x, xd, aU, aJ, nullptr, st);
+    if (!r) r = rk_stage(c, 1, dt_dev, JU, J, aU, aJ, x, xd, bU, bJ, nullptr, st);
+    if (!r) r = rk_stage(c, 2, dt_dev, JU, J, bU, bJ, x, xd, JU, J, nullptr, st);
+    return r;
+  }
+  // moving mesh: the three rk_stage calls, with each stage's update kernel also forming the
+  // next stage's mesh x_n + c_{s+1} dt xdot (c = 0, 1, 1/2, then 1 for x^{n+1}) instead of a
+  // separate launch; the stage-1 update overwrites the stage mesh its own node kernel has read
+  if (launch_rhs_mesh(c, JU, J, nullptr, nullptr, x, xd, 0.0, 1, 0, dt_dev, JU, J, aU, aJ, x, xd, 1.0, c->xtmp, st) ||
+      launch_rhs_mesh(c, aU, aJ, nullptr, nullptr, c->xtmp, xd, 0.0, 1, 1, dt_dev, JU, J, bU, bJ, x, xd, 0.5, c->xtmp,
+                      st) ||
+      launch_rhs_mesh(c, bU, bJ, nullptr, nullptr, c->xtmp, xd, 0.0, 1, 2, dt_dev, JU, J, JU, J, x, xd, 1.0, x, st))
+    return ESVDW_EHIP;
+  return ESVDW_OK;
 }
 
 int esvdw_bench_kernel(esvdw_ctx *c, int which, int reps, hipStream_t st) {

@@ -11,6 +11,11 @@ int launch_metrics(esvdw_ctx *c, const double *x, const double *xd, double *met,
 int launch_rhs(esvdw_ctx *c, const double *JU, const double *J, const double *met, const double *xit,
                const double *xn, const double *xd, double cdt, int mode, int s, const double *dtp,
                const double *bJU, const double *bJ, double *oJU, double *oJ, hipStream_t st);
+// launch_rhs whose update kernel also writes the next stage's mesh mout = mx + mf dt mxd per node
+int launch_rhs_mesh(esvdw_ctx *c, const double *JU, const double *J, const double *met, const double *xit,
+                    const double *xn, const double *xd, double cdt, int mode, int s, const double *dtp,
+                    const double *bJU, const double *bJ, double *oJU, double *oJ, const double *mx, const double *mxd,
+                    double mf, double *mout, hipStream_t st);
 int launch_uniform_mesh(esvdw_ctx *c, double *x, hipStream_t st);
 int launch_init_state(esvdw_ctx *c, const double *prim, const double *J, double *JU, hipStream_t st);
 int launch_axpy_mesh(esvdw_ctx *c, const double *x, const double *xd, const double *dtp, double f, double *out,

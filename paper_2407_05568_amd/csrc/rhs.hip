@@ -103,11 +103,17 @@ __global__ void k_update(Geo G, const double *__restrict__ F0, const double *__r
                          const double *__restrict__ dtp, const double *__restrict__ base_JU,
                          const double *__restrict__ base_J, const double *__restrict__ in_JU,
                          const double *__restrict__ in_J, double *__restrict__ out_JU, double *__restrict__ out_J,
-                         unsigned *flags) {
+                         unsigned *flags, const double *mx, const double *mxd, double mf, double *mout) {
   NODE_COORDS(G.n[0], G.n[1]);
   if (!inside) return;
   update_point<D>(G, F0, F1, F2, nif0, nif1, nif2, mode, s, dtp, base_JU, base_J, in_JU, in_J, out_JU, out_J, flags,
                   i0, i1, i2);
+  if (mout) {
+    // the next stage's mesh x_n + f dt xdot at this node (k_axpy_mesh's arithmetic; mout may be mx)
+    const long t = lin(G, i0, i1, i2);
+#pragma unroll
+    for (int j = 0; j < D; ++j) mout[(long)j * G.N + t] = mx[(long)j * G.N + t] + mf * (*dtp) * mxd[(long)j * G.N + t];
+  }
 }
 
 // =============================== small kernels ===================================
@@ -188,7 +194,8 @@ template <int D> static void launch_flux_d(esvdw_ctx *c, int K, hipStream_t st) 
 template <int D>
 static int rhs_pipeline_d(esvdw_ctx *c, const double *JU, const double *J, const double *met, const double *xit,
                           const double *xn, const double *xd, double cdt, int mode, int s, const double *dtp,
-                          const double *bJU, const double *bJ, double *oJU, double *oJ, hipStream_t st) {
+                          const double *bJU, const double *bJ, double *oJU, double *oJ, const double *mx,
+                          const double *mxd, double mf, double *mout, hipStream_t st) {
   const Geo &G = c->G;
   if (!met && D == 3)
     if (launch_dprod(c, xn, xd, cdt, st)) return -1;
@@ -200,18 +207,27 @@ static int rhs_pipeline_d(esvdw_ctx *c, const double *JU, const double *J, const
   if (D > 1) launch_flux_d<D>(c, 1, st);
   if (D > 2) launch_flux_d<D>(c, 2, st);
   hipLaunchKernelGGL(k_update<D>, gu, bu, 0, st, G, c->flux[0], c->flux[1], c->flux[2],
-                     c->nif[0], c->nif[1], c->nif[2], mode, s, dtp, bJU, bJ, JU, J, oJU, oJ, c->flags);
+                     c->nif[0], c->nif[1], c->nif[2], mode, s, dtp, bJU, bJ, JU, J, oJU, oJ, c->flags, mx, mxd, mf,
+                     mout);
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_rhs_mesh(esvdw_ctx *c, const double *JU, const double *J, const double *met, const double *xit,
+                    const double *xn, const double *xd, double cdt, int mode, int s, const double *dtp,
+                    const double *bJU, const double *bJ, double *oJU, double *oJ, const double *mx, const double *mxd,
+                    double mf, double *mout, hipStream_t st) {
+  switch (c->G.dim) {
+    case 1: return rhs_pipeline_d<1>(c, JU, J, met, xit, xn, xd, cdt, mode, s, dtp, bJU, bJ, oJU, oJ, mx, mxd, mf, mout, st);
+    case 2: return rhs_pipeline_d<2>(c, JU, J, met, xit, xn, xd, cdt, mode, s, dtp, bJU, bJ, oJU, oJ, mx, mxd, mf, mout, st);
+    default: return rhs_pipeline_d<3>(c, JU, J, met, xit, xn, xd, cdt, mode, s, dtp, bJU, bJ, oJU, oJ, mx, mxd, mf, mout, st);
+  }
 }
 
 int launch_rhs(esvdw_ctx *c, const double *JU, const double *J, const double *met, const double *xit,
                const double *xn, const double *xd, double cdt, int mode, int s, const double *dtp,
                const double *bJU, const double *bJ, double *oJU, double *oJ, hipStream_t st) {
-  switch (c->G.dim) {
-    case 1: return rhs_pipeline_d<1>(c, JU, J, met, xit, xn, xd, cdt, mode, s, dtp, bJU, bJ, oJU, oJ, st);
-    case 2: return rhs_pipeline_d<2>(c, JU, J, met, xit, xn, xd, cdt, mode, s, dtp, bJU, bJ, oJU, oJ, st);
-    default: return rhs_pipeline_d<3>(c, JU, J, met, xit, xn, xd, cdt, mode, s, dtp, bJU, bJ, oJU, oJ, st);
-  }
+  return launch_rhs_mesh(c, JU, J, met, xit, xn, xd, cdt, mode, s, dtp, bJU, bJ, oJU, oJ, nullptr, nullptr, 0.0,
+                         nullptr, st);
 }
 
 int launch_uniform_mesh(esvdw_ctx *c, double *x, hipStream_t st) {
