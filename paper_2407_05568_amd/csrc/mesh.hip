@@ -379,6 +379,28 @@ __global__ void k_cfl(Geo G, const double *__restrict__ JU, const double *__rest
   if (flat_tid() == 0) part[flat_bid()] = ms;
 }
 
+// k_final (maxima) for several partial arrays at once: block q reduces part + q * stride into dst[q]
+__global__ void k_final_many(const double *__restrict__ part, long stride, long nb, double *dst) {
+  const double *pq = part + blockIdx.x * stride;
+  double v = 0.0;
+  for (long i = threadIdx.x; i < nb; i += blockDim.x) v = fmax(v, pq[i]);
+  v = block_max(v);
+  if (threadIdx.x == 0) dst[blockIdx.x] = v;
+}
+
+// k_final for the CFL maxima followed by k_dt's dt = cfl / max, in one launch
+__global__ void k_final_dt(const double *__restrict__ part, long nb, double cfl, double *scal, double *dt_out) {
+  double v = 0.0;
+  for (long i = threadIdx.x; i < nb; i += blockDim.x) v = fmax(v, part[i]);
+  v = block_max(v);
+  if (threadIdx.x == 0) {
+    scal[SC_CFL] = v;
+    double dt = cfl / scal[SC_CFL];
+    scal[SC_DT] = dt;
+    if (dt_out) *dt_out = dt;
+  }
+}
+
 __global__ void k_dt(double cfl, double dt_fixed, double *scal, double *dt_out) {
   if (threadIdx.x == 0) {
     double dt = dt_fixed > 0.0 ? dt_fixed : cfl / scal[SC_CFL];
@@ -426,8 +448,7 @@ template <int D> static int monitor_d(esvdw_ctx *c, const double *JU, const doub
   int nterm = p.monitor_kind == ESVDW_MON_VDW ? p.kappa + 1 : 2;
   hipLaunchKernelGGL(k_mon_terms<D>, g, b, 0, st, G, p.monitor_kind, p.kappa, p.mon_var[0], p.mon_var[1], c->rhoG,
                      c->mterm, c->part, c->npart);
-  for (int q = 0; q < nterm; ++q)
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, c->part + q * c->npart, nb, c->scal + SC_MON + q, 0);
+  hipLaunchKernelGGL(k_final_many, dim3(nterm), dim3(1024), 0, st, c->part, c->npart, nb, c->scal + SC_MON);
   // 2D outflow grids run up to JT_H passes per launch; the filtered result must end in `omega`:
   // start in omega2 when the launch count is odd
   const bool multi = D == 2 && G.bc[0] != ESVDW_BC_PERIODIC && G.bc[1] != ESVDW_BC_PERIODIC && p.n_filter >= 2;
@@ -548,9 +569,10 @@ int launch_cfl(esvdw_ctx *c, const double *JU, const double *J, const double *x,
     if (G.dim == 1) hipLaunchKernelGGL(k_cfl<1>, g, b, 0, st, G, JU, J, x, c->met, c->part);
     else if (G.dim == 2) hipLaunchKernelGGL(k_cfl<2>, g, b, 0, st, G, JU, J, x, c->met, c->part);
     else hipLaunchKernelGGL(k_cfl<3>, g, b, 0, st, G, JU, J, x, c->met, c->part);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, c->part, nb, c->scal + SC_CFL, 0);
+    hipLaunchKernelGGL(k_final_dt, dim3(1), dim3(1024), 0, st, c->part, nb, c->p.cfl, c->scal, dt_dev);
+  } else {
+    hipLaunchKernelGGL(k_dt, dim3(1), dim3(64), 0, st, c->p.cfl, c->p.dt_fixed, c->scal, dt_dev);
   }
-  hipLaunchKernelGGL(k_dt, dim3(1), dim3(64), 0, st, c->p.cfl, c->p.dt_fixed, c->scal, dt_dev);
   return CHK();
 }
 
