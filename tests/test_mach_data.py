@@ -1,0 +1,32 @@
+"""Table 5.3 (Example 5.4) read in reduced units with the paper's velocities scaled by sqrt(8/3):
+each case's two states form a shock that satisfies the Rankine-Hugoniot mass, momentum and
+energy balances, moving at the printed Mach number into the state at rest.  This pins the unit
+reading the Mach-reflection set-up relies on: with the printed velocities left unscaled, the
+momentum balance would be off by the factor 8/3."""
+import math
+
+import pytest
+
+from paper_2407_05568_amd import synth
+
+
+@pytest.mark.parametrize("case", ["P1", "D1"])
+def test_table_5_3_states_are_a_shock_at_the_printed_mach_number(orc, case):
+    c = synth.TABLE_5_3[case]
+    p = synth.problem(1, [8], bc="outflow", delta=c["gamma"] - 1.0)
+    o = orc.Oracle(p)
+    rl, ul, _, pl = c["left"]
+    rr, ur, _, pr = c["right"]
+    ul *= math.sqrt(8.0 / 3.0)
+    S = rl * ul / (rl - rr)  # mass balance across the front (the state ahead is at rest)
+    # momentum: p_l - p_r = rho_r S u_l (the state ahead at rest)
+    assert pl - pr == pytest.approx(rr * S * ul, rel=0.02)
+    # energy: S (E_l - E_r) = (E_l + p_l) u_l with the oracle's EOS (the printed states carry 3-4
+    # digits, so the balance holds to about 1% of its terms)
+    El = o.prim_to_cons([rl, ul, pl])[2]
+    Er = o.prim_to_cons([rr, 0.0, pr])[2]
+    assert El * (S - ul) - Er * S - pl * ul == pytest.approx(0.0, abs=0.02 * abs(El * (S - ul)))
+    # Mach number of the front relative to the sound speed of the state ahead
+    Tr = o.T_from_rho_p(rr, pr)
+    cr = math.sqrt(o.eos_state(rr, Tr)["c2"])
+    assert abs(S) / cr == pytest.approx(c["mach"], rel=0.02)
