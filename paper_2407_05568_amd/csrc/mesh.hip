@@ -243,7 +243,7 @@ __global__ void __launch_bounds__(256) k_jacobi_multi2(Geo G, const double *__re
 __global__ void __launch_bounds__(256) k_filter_multi2(Geo G, const double *__restrict__ in, double *__restrict__ out,
                                                        int npass) {
   __shared__ double sa[2][JT_NE];
-  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
+  const int tx = threadIdx.x, ty = threadIdx.y;
   const int exn = JT_X + 2 * npass, eyn = JT_Y + 2 * npass;
   const int gx0 = blockIdx.x * JT_X - npass, gy0 = blockIdx.y * JT_Y - npass;
   const int n0 = G.n[0], n1 = G.n[1];

@@ -12,25 +12,92 @@
 
 // 3D: dprod[q*3 + j] = delta_q[x_{j+1}] x_{j+2} (indices mod 3), the inner products of the
 // nested metric form, on a grid padded by 6 in every direction (valid where the q index is
-// within 3 of the interior, which is where it is used)
-__global__ void k_dprod(Geo G, const double *__restrict__ xn, const double *__restrict__ xd, double cdt,
-                        double *__restrict__ dp, long dpN) {
-  const int P0 = G.n[0] + 12, P1 = G.n[1] + 12;
-  NODE_COORDS(P0, P1);
-  if (!inside) return;
-  const long t = ((long)i2 * P1 + i1) * P0 + i0;
-  {
-  const int i0 = (int)(blockIdx.x * blockDim.x + threadIdx.x) - 6,
-            i1 = (int)(blockIdx.y * blockDim.y + threadIdx.y) - 6, i2 = (int)blockIdx.z - 6;
-  int ii[3] = {i0, i1, i2};
-  const double xs[3] = {stage_x(G, xn, xd, cdt, 0, i0, i1, i2), stage_x(G, xn, xd, cdt, 1, i0, i1, i2),
-                        stage_x(G, xn, xd, cdt, 2, i0, i1, i2)};
-  for (int q = 0; q < 3; ++q) {
-    bool ok = ii[q] >= -3 && ii[q] < G.n[q] + 3;
-    for (int j = 0; j < 3; ++j)
-      dp[(long)(q * 3 + j) * dpN + t] =
-          ok ? delta_x(G, xn, xd, cdt, q, (j + 1) % 3, i0, i1, i2) * xs[(j + 2) % 3] : 0.0;
-  }
+// within 3 of the interior, which is where it is used; zero elsewhere).
+//
+// A block covers DP_TX x DP_TY padded columns (i0, i1) and marches along i2 through DP_TZ
+// output planes.  Each plane of the stage mesh is staged in LDS with a 3-node halo in i0 and
+// i1, from which delta_0 and delta_1 are taken; each thread keeps the last seven planes of its
+// own column in registers for delta_2.  A stage-mesh value is thus read from memory about 1.6
+// times per padded node (halo and the six warm-up planes of a chunk) instead of 54 times.
+// The values and the order of every sum are those of delta_x and stage_x.
+#define DP_TX 32
+#define DP_TY 16
+#define DP_TZ 24
+
+__device__ __forceinline__ double delta_of(double p1, double m1, double p2, double m2, double p3, double m3) {
+  double s = 0.0;
+  s += AL1 * (p1 - m1);
+  s += AL2 * (p2 - m2);
+  s += AL3 * (p3 - m3);
+  return 0.5 * s;
+}
+
+__global__ void __launch_bounds__(DP_TX * DP_TY) k_dprod(Geo G, const double *__restrict__ xn,
+                                                        const double *__restrict__ xd, double cdt,
+                                                        double *__restrict__ dp, long dpN) {
+  __shared__ double sx[3][DP_TY + 6][DP_TX + 6];
+  const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
+  const int P0 = n0 + 12, P1 = n1 + 12;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * DP_TX + tx;
+  const int b0 = (int)blockIdx.x * DP_TX - 6, b1 = (int)blockIdx.y * DP_TY - 6;  // first column of the tile
+  const int i0 = b0 + tx, i1 = b1 + ty;
+  const bool col = i0 < n0 + 6 && i1 < n1 + 6;
+  const bool ok0 = i0 >= -3 && i0 < n0 + 3, ok1 = i1 >= -3 && i1 < n1 + 3;
+  const int z0 = (int)blockIdx.z * DP_TZ - 6, z1 = min(z0 + DP_TZ, n2 + 6);  // output planes [z0, z1)
+  const int pa = max(z0 - 3, -6), pe = z1 + 3;
+  double ring[3][7];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int r = 0; r < 7; ++r) ring[j][r] = 0.0;
+  const long tcol = (long)(i1 + 6) * P0 + (i0 + 6);
+  for (int p = pa; p < pe; ++p) {
+    const bool have = p < n2 + 6;  // planes beyond the padded grid feed only zero outputs
+    if (have) {
+      for (int idx = tid; idx < (DP_TX + 6) * (DP_TY + 6); idx += DP_TX * DP_TY) {
+        const int a = idx % (DP_TX + 6), b = idx / (DP_TX + 6);
+        const int g0 = b0 - 3 + a, g1 = b1 - 3 + b;
+        const bool in = g0 >= -6 && g0 < n0 + 6 && g1 >= -6 && g1 < n1 + 6;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) sx[j][b][a] = in ? stage_x(G, xn, xd, cdt, j, g0, g1, p) : 0.0;
+      }
+    }
+    __syncthreads();
+    double xc[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      xc[j] = have ? sx[j][ty + 3][tx + 3] : 0.0;
+#pragma unroll
+      for (int r = 0; r < 6; ++r) ring[j][r] = ring[j][r + 1];
+      ring[j][6] = xc[j];
+    }
+    if (col && p >= z0 && p < z1) {
+      const long t = (long)(p + 6) * P1 * P0 + tcol;
+      double d[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        d[j] = delta_of(sx[j][ty + 3][tx + 4], sx[j][ty + 3][tx + 2], sx[j][ty + 3][tx + 5], sx[j][ty + 3][tx + 1],
+                        sx[j][ty + 3][tx + 6], sx[j][ty + 3][tx]);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) dp[(long)j * dpN + t] = ok0 ? d[(j + 1) % 3] * xc[(j + 2) % 3] : 0.0;
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        d[j] = delta_of(sx[j][ty + 4][tx + 3], sx[j][ty + 2][tx + 3], sx[j][ty + 5][tx + 3], sx[j][ty + 1][tx + 3],
+                        sx[j][ty + 6][tx + 3], sx[j][ty][tx + 3]);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) dp[(long)(3 + j) * dpN + t] = ok1 ? d[(j + 1) % 3] * xc[(j + 2) % 3] : 0.0;
+    }
+    const int z = p - 3;  // the plane whose delta_2 the ring now spans
+    if (col && z >= z0 && z < z1) {
+      const long t = (long)(z + 6) * P1 * P0 + tcol;
+      const bool ok2 = z >= -3 && z < n2 + 3;
+      double d[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) d[j] = delta_of(ring[j][4], ring[j][2], ring[j][5], ring[j][1], ring[j][6], ring[j][0]);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) dp[(long)(6 + j) * dpN + t] = ok2 ? d[(j + 1) % 3] * ring[(j + 2) % 3][3] : 0.0;
+    }
+    __syncthreads();
   }
 }
 
@@ -157,8 +224,8 @@ static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b);
 
 int launch_dprod(esvdw_ctx *c, const double *xn, const double *xd, double cdt, hipStream_t st) {
   if (c->G.dim != 3) return 0;
-  dim3 g, b;
-  node_grid(c->G.n[0] + 12, c->G.n[1] + 12, c->G.n[2] + 12, g, b);
+  const int P0 = c->G.n[0] + 12, P1 = c->G.n[1] + 12, P2 = c->G.n[2] + 12;
+  dim3 g((P0 + DP_TX - 1) / DP_TX, (P1 + DP_TY - 1) / DP_TY, (P2 + DP_TZ - 1) / DP_TZ), b(DP_TX, DP_TY);
   hipLaunchKernelGGL(k_dprod, g, b, 0, st, c->G, xn, xd, cdt, c->dprod, c->dpN);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
