@@ -53,13 +53,26 @@ __global__ void __launch_bounds__(DP_TX * DP_TY) k_dprod(Geo G, const double *__
   const long tcol = (long)(i1 + 6) * P0 + (i0 + 6);
   for (int p = pa; p < pe; ++p) {
     const bool have = p < n2 + 6;  // planes beyond the padded grid feed only zero outputs
-    if (have) {
-      for (int idx = tid; idx < (DP_TX + 6) * (DP_TY + 6); idx += DP_TX * DP_TY) {
+    if (have) {  // all loads of the plane are issued before the first LDS store
+      constexpr int NS = (DP_TX + 6) * (DP_TY + 6), NIT = (NS + DP_TX * DP_TY - 1) / (DP_TX * DP_TY);
+      double v[NIT][3];
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        const int idx = tid + it * DP_TX * DP_TY;
         const int a = idx % (DP_TX + 6), b = idx / (DP_TX + 6);
         const int g0 = b0 - 3 + a, g1 = b1 - 3 + b;
-        const bool in = g0 >= -6 && g0 < n0 + 6 && g1 >= -6 && g1 < n1 + 6;
+        const bool in = idx < NS && g0 >= -6 && g0 < n0 + 6 && g1 >= -6 && g1 < n1 + 6;
 #pragma unroll
-        for (int j = 0; j < 3; ++j) sx[j][b][a] = in ? stage_x(G, xn, xd, cdt, j, g0, g1, p) : 0.0;
+        for (int j = 0; j < 3; ++j) v[it][j] = in ? stage_x(G, xn, xd, cdt, j, g0, g1, p) : 0.0;
+      }
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        const int idx = tid + it * DP_TX * DP_TY;
+        if (idx < NS) {
+          const int a = idx % (DP_TX + 6), b = idx / (DP_TX + 6);
+#pragma unroll
+          for (int j = 0; j < 3; ++j) sx[j][b][a] = v[it][j];
+        }
       }
     }
     __syncthreads();
