@@ -127,18 +127,20 @@ __device__ __forceinline__ double metric_at(const Geo &G, const double *xn, cons
   // D == 3: (delta_{k2}[delta_{k1}[x_{j1}] x_{j2}] - delta_{k1}[delta_{k2}[x_{j1}] x_{j2}]) / (dxi_{k1} dxi_{k2})
   int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
   const double al[3] = {AL1, AL2, AL3};
+  // dp holds delta_in[x_{j+1}] x_{j+2} at every padded node; the stencil is the node's own
+  // index plus or minus m strides along `out`
+  const long c = dp_index(G, i0, i1, i2);
+  const long stride[3] = {1, (long)(G.n[0] + 12), (long)(G.n[0] + 12) * (G.n[1] + 12)};
   double s = 0.0;
   for (int term = 0; term < 2; ++term) {
     int in = term == 0 ? k1 : k2, out = term == 0 ? k2 : k1;
-    int e[3] = {out == 0, out == 1, out == 2};
+    const double *f = dp + (long)(in * 3 + j) * dpN + c;
+    const long st = stride[out];
     double acc = 0.0;
 #pragma unroll
     for (int m = 1; m <= 3; ++m) {
-      int a0 = i0 + m * e[0], a1 = i1 + m * e[1], a2 = i2 + m * e[2];
-      int b0 = i0 - m * e[0], b1 = i1 - m * e[1], b2 = i2 - m * e[2];
-      // dp holds delta_in[x_{j+1}] x_{j+2} at every padded node
-      double fa = dp[(long)(in * 3 + j) * dpN + dp_index(G, a0, a1, a2)];
-      double fb = dp[(long)(in * 3 + j) * dpN + dp_index(G, b0, b1, b2)];
+      double fa = f[m * st];
+      double fb = f[-m * st];
       acc += al[m - 1] * (fa - fb);
     }
     s += (term == 0 ? 0.5 : -0.5) * acc;
