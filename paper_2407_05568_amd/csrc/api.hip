@@ -228,12 +228,14 @@ int redistribute_mesh(esvdw_ctx *c, const double *JU, const double *J, const dou
   const esvdw_params &p = c->p;
   long n = (long)c->G.dim * c->G.N;
   if (launch_monitor(c, JU, J, c->omega, st)) return ESVDW_EHIP;
+  // x^[0] = x_n (+ warm_dx); with a fixed sweep count and no warm start the first sweep reads x_n
+  const bool from_xn = p.fixed_mu && !warm_dx;
   if (warm_dx) {
     if (launch_add(x_n, warm_dx, c->xmu, n, st)) return ESVDW_EHIP;
-  } else if (launch_copy(x_n, c->xmu, n, st)) return ESVDW_EHIP;
+  } else if (!from_xn && launch_copy(x_n, c->xmu, n, st)) return ESVDW_EHIP;
   int sweeps = 0;
   if (p.fixed_mu) {
-    if (launch_jacobi(c, c->omega, c->xmu, p.mu, resid_dev, st)) return ESVDW_EHIP;
+    if (launch_jacobi_from(c, c->omega, from_xn ? x_n : nullptr, c->xmu, p.mu, resid_dev, st)) return ESVDW_EHIP;
     sweeps = p.mu;
   } else {
     // tolerance mode: batches of sweeps, host-side test of the device residual

@@ -25,6 +25,9 @@ int launch_set_int(int *p, int v, hipStream_t st);
 int launch_set_scalars(esvdw_ctx *c, hipStream_t st);
 int launch_monitor(esvdw_ctx *c, const double *JU, const double *J, double *omega, hipStream_t st);
 int launch_jacobi(esvdw_ctx *c, const double *omega, double *x, int nsweep, double *resid_dev, hipStream_t st);
+// nsweep sweeps from the iterate x0 (not modified; nullptr = x), the result in x
+int launch_jacobi_from(esvdw_ctx *c, const double *omega, const double *x0, double *x, int nsweep, double *resid_dev,
+                       hipStream_t st);
 int launch_sor(esvdw_ctx *c, const double *omega, double *x, int nsweep, double relax, double *resid_dev,
                hipStream_t st);
 int launch_limiter(esvdw_ctx *c, const double *xn, const double *xmu, double *gamma_dev, hipStream_t st);

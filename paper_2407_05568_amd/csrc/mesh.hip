@@ -478,11 +478,15 @@ int launch_monitor(esvdw_ctx *c, const double *JU, const double *J, double *omeg
 }
 
 template <int D>
-static int jacobi_d(esvdw_ctx *c, const double *omega, double *x, int nsweep, double *resid_dev, hipStream_t st) {
+static int jacobi_d(esvdw_ctx *c, const double *omega, const double *x0, double *x, int nsweep, double *resid_dev,
+                    hipStream_t st) {
   const Geo &G = c->G;
   dim3 b, g;
   node_grid(G.n[0], G.n[1], G.n[2], g, b);
   const long nb = (long)g.x * g.y * g.z;
+  // the first launch reads x0 (when given) and writes the scratch iterate; later ones alternate
+  // between x and the scratch, so x0 is never written
+  const double *a0 = x0 ? x0 : x;
   double *a = x, *o = c->xtmp;
   const bool multi = D == 2 && G.bc[0] != ESVDW_BC_PERIODIC && G.bc[1] != ESVDW_BC_PERIODIC && nsweep >= 2;
   if (multi) {
@@ -491,7 +495,8 @@ static int jacobi_d(esvdw_ctx *c, const double *omega, double *x, int nsweep, do
     for (int done = 0; done < nsweep;) {
       const int k = nsweep - done < JT_H ? nsweep - done : JT_H;
       const bool last = done + k == nsweep;
-      hipLaunchKernelGGL(k_jacobi_multi2, gm, dim3(64, 4), 0, st, G, omega, a, o, k, last ? c->part : nullptr);
+      hipLaunchKernelGGL(k_jacobi_multi2, gm, dim3(64, 4), 0, st, G, omega, done == 0 ? a0 : a, o, k,
+                         last ? c->part : nullptr);
       if (last) hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, c->part, nbm, c->scal + SC_RESID, 0);
       double *tmp = a;
       a = o;
@@ -501,13 +506,14 @@ static int jacobi_d(esvdw_ctx *c, const double *omega, double *x, int nsweep, do
   }
   for (int it = 0; !multi && it < nsweep; ++it) {
     bool last = it == nsweep - 1;
-    hipLaunchKernelGGL(k_jacobi<D>, g, b, 0, st, G, omega, a, o, last ? c->part : nullptr);
+    hipLaunchKernelGGL(k_jacobi<D>, g, b, 0, st, G, omega, it == 0 ? a0 : a, o, last ? c->part : nullptr);
     if (last) hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, c->part, nb, c->scal + SC_RESID, 0);
     double *tmp = a;
     a = o;
     o = tmp;
   }
   if (a != x) launch_copy(a, x, (long)D * G.N, st);
+  else if (nsweep == 0 && x0 && x0 != x) launch_copy(x0, x, (long)D * G.N, st);
   if (resid_dev) launch_copy(c->scal + SC_RESID, resid_dev, 1, st);
   return CHK();
 }
@@ -538,12 +544,17 @@ int launch_sor(esvdw_ctx *c, const double *omega, double *x, int nsweep, double 
   }
 }
 
-int launch_jacobi(esvdw_ctx *c, const double *omega, double *x, int nsweep, double *resid_dev, hipStream_t st) {
+int launch_jacobi_from(esvdw_ctx *c, const double *omega, const double *x0, double *x, int nsweep, double *resid_dev,
+                       hipStream_t st) {
   switch (c->G.dim) {
-    case 1: return jacobi_d<1>(c, omega, x, nsweep, resid_dev, st);
-    case 2: return jacobi_d<2>(c, omega, x, nsweep, resid_dev, st);
-    default: return jacobi_d<3>(c, omega, x, nsweep, resid_dev, st);
+    case 1: return jacobi_d<1>(c, omega, x0, x, nsweep, resid_dev, st);
+    case 2: return jacobi_d<2>(c, omega, x0, x, nsweep, resid_dev, st);
+    default: return jacobi_d<3>(c, omega, x0, x, nsweep, resid_dev, st);
   }
+}
+
+int launch_jacobi(esvdw_ctx *c, const double *omega, double *x, int nsweep, double *resid_dev, hipStream_t st) {
+  return launch_jacobi_from(c, omega, nullptr, x, nsweep, resid_dev, st);
 }
 
 int launch_limiter(esvdw_ctx *c, const double *xn, const double *xmu, double *gamma_dev, hipStream_t st) {
