@@ -494,7 +494,7 @@ static int jacobi_d(esvdw_ctx *c, const double *omega, const double *x0, double 
     const long nbm = (long)gm.x * gm.y;  // <= 4 npart
     for (int done = 0; done < nsweep;) {
       const int k = nsweep - done < JT_H ? nsweep - done : JT_H;
-      const bool last = done + k == nsweep;
+      const bool last = done + k == nsweep && resid_dev;  // the residual only when asked for
       hipLaunchKernelGGL(k_jacobi_multi2, gm, dim3(64, 4), 0, st, G, omega, done == 0 ? a0 : a, o, k,
                          last ? c->part : nullptr);
       if (last) hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, c->part, nbm, c->scal + SC_RESID, 0);
@@ -505,7 +505,7 @@ static int jacobi_d(esvdw_ctx *c, const double *omega, const double *x0, double 
     }
   }
   for (int it = 0; !multi && it < nsweep; ++it) {
-    bool last = it == nsweep - 1;
+    bool last = it == nsweep - 1 && resid_dev;
     hipLaunchKernelGGL(k_jacobi<D>, g, b, 0, st, G, omega, it == 0 ? a0 : a, o, last ? c->part : nullptr);
     if (last) hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, c->part, nb, c->scal + SC_RESID, 0);
     double *tmp = a;
