@@ -259,8 +259,7 @@ int redistribute_mesh(esvdw_ctx *c, const double *JU, const double *J, const dou
     if (resid_dev && launch_copy(c->scal + SC_N - 1, resid_dev, 1, st)) return ESVDW_EHIP;
   }
   if (sweeps_dev && launch_set_int(sweeps_dev, sweeps, st)) return ESVDW_EHIP;
-  if (launch_limiter(c, x_n, c->xmu, nullptr, st)) return ESVDW_EHIP;
-  if (launch_cfl(c, JU, J, x_n, dt_dev, st)) return ESVDW_EHIP;
+  if (launch_limiter_cfl(c, x_n, c->xmu, JU, J, dt_dev, st)) return ESVDW_EHIP;
   if (launch_xdot(c, x_n, c->xmu, c->scal + SC_GAMMA, dt_dev, xdot, st)) return ESVDW_EHIP;
   return ESVDW_OK;
 }

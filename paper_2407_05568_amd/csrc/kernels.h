@@ -31,6 +31,10 @@ int launch_jacobi_from(esvdw_ctx *c, const double *omega, const double *x0, doub
 int launch_sor(esvdw_ctx *c, const double *omega, double *x, int nsweep, double relax, double *resid_dev,
                hipStream_t st);
 int launch_limiter(esvdw_ctx *c, const double *xn, const double *xmu, double *gamma_dev, hipStream_t st);
+// launch_limiter (gamma into the context's scalars) followed by launch_cfl, the two final
+// reductions in one launch
+int launch_limiter_cfl(esvdw_ctx *c, const double *xn, const double *xmu, const double *JU, const double *J,
+                       double *dt_dev, hipStream_t st);
 int launch_cfl(esvdw_ctx *c, const double *JU, const double *J, const double *x, double *dt_dev, hipStream_t st);
 int launch_xdot(esvdw_ctx *c, const double *xn, const double *xmu, const double *gam, const double *dtp, double *xdot,
                 hipStream_t st);

@@ -401,6 +401,25 @@ __global__ void k_final_dt(const double *__restrict__ part, long nb, double cfl,
   }
 }
 
+// k_final's movement-limiter minimum and k_final_dt's CFL maximum and dt in one launch (the
+// same reductions in the same order)
+__global__ void k_final_gamma_dt(const double *__restrict__ pl, long nbl, const double *__restrict__ pc, long nbc,
+                                 double cfl, double *scal, double *dt_out) {
+  double g = 1.0;
+  for (long i = threadIdx.x; i < nbl; i += blockDim.x) g = fmin(g, pl[i]);
+  g = block_min(g);
+  double v = 0.0;
+  for (long i = threadIdx.x; i < nbc; i += blockDim.x) v = fmax(v, pc[i]);
+  v = block_max(v);
+  if (threadIdx.x == 0) {
+    scal[SC_GAMMA] = g;
+    scal[SC_CFL] = v;
+    double dt = cfl / scal[SC_CFL];
+    scal[SC_DT] = dt;
+    if (dt_out) *dt_out = dt;
+  }
+}
+
 __global__ void k_dt(double cfl, double dt_fixed, double *scal, double *dt_out) {
   if (threadIdx.x == 0) {
     double dt = dt_fixed > 0.0 ? dt_fixed : cfl / scal[SC_CFL];
@@ -584,6 +603,28 @@ int launch_cfl(esvdw_ctx *c, const double *JU, const double *J, const double *x,
   } else {
     hipLaunchKernelGGL(k_dt, dim3(1), dim3(64), 0, st, c->p.cfl, c->p.dt_fixed, c->scal, dt_dev);
   }
+  return CHK();
+}
+
+int launch_limiter_cfl(esvdw_ctx *c, const double *xn, const double *xmu, const double *JU, const double *J,
+                       double *dt_dev, hipStream_t st) {
+  const Geo &G = c->G;
+  if (c->p.dt_fixed > 0.0) {
+    if (launch_limiter(c, xn, xmu, nullptr, st)) return -1;
+    return launch_cfl(c, JU, J, xn, dt_dev, st);
+  }
+  dim3 b, g;
+  node_grid(G.n[0], G.n[1], G.n[2], g, b);
+  const long nb = (long)g.x * g.y * g.z;
+  double *pc = c->part + 3 * c->npart;  // the CFL partials beside the limiter's
+  if (G.dim == 1) hipLaunchKernelGGL(k_limiter<1>, g, b, 0, st, G, xn, xmu, c->part);
+  else if (G.dim == 2) hipLaunchKernelGGL(k_limiter<2>, g, b, 0, st, G, xn, xmu, c->part);
+  else hipLaunchKernelGGL(k_limiter<3>, g, b, 0, st, G, xn, xmu, c->part);
+  if (G.dim == 3 && launch_metrics(c, xn, nullptr, c->met, nullptr, nullptr, st)) return -1;
+  if (G.dim == 1) hipLaunchKernelGGL(k_cfl<1>, g, b, 0, st, G, JU, J, xn, c->met, pc);
+  else if (G.dim == 2) hipLaunchKernelGGL(k_cfl<2>, g, b, 0, st, G, JU, J, xn, c->met, pc);
+  else hipLaunchKernelGGL(k_cfl<3>, g, b, 0, st, G, JU, J, xn, c->met, pc);
+  hipLaunchKernelGGL(k_final_gamma_dt, dim3(1), dim3(1024), 0, st, c->part, nb, pc, nb, c->p.cfl, c->scal, dt_dev);
   return CHK();
 }
 
