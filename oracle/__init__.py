@@ -115,6 +115,8 @@ def lib():
             "orc_jacobian": (None, [_CP, _D, _D]),
             "orc_uniform_mesh": (None, [_CP, _D]),
             "orc_rhs": (None, [_CP, _D, _D, _D, _D, _D, _D, _D]),
+            "orc_rhs_record": (None, [_CP, _D, _D, _D, _D, _D, _D, _D]),
+            "orc_interface_flux": (None, [_CP, _D, _D, _D, _D, _D, _D, _D]),
             "orc_rk_stage": (None, [_CP, ctypes.c_int, ctypes.c_double, _D, _D, _D, _D, _D, _D, _D, _D]),
             "orc_cfl_dt": (ctypes.c_double, [_CP, _D, _D, _D]),
             "orc_monitor": (None, [_CP, _D, _D, _D]),
@@ -253,6 +255,46 @@ class Oracle:
         self.L.orc_rhs(self._cp(), _p(_arr(JU)), _p(_arr(J)), _p(_arr(met)),
                        _p(None if xit is None else _arr(xit)), _p(dJU), _p(dJ), _p(prod))
         return (dJU, dJ, prod[0]) if want_prod else (dJU, dJ)
+
+    def rhs_record(self, JU, J, met, xit=None):
+        """Per-interface records behind rhs(): a list over directions k of dicts with arrays of
+        shape (nv,) + interface grid (n_k + 1 along k): F (entropy-stable flux), gcl (shape of the
+        grid), Y (sign matrix), jw ([W]^WENO), j0 (plain jump before its zero test), scale (the
+        zero test's rounding scale).  Also returns (dJU, dJ)."""
+        d, nv = self.d, self.nv
+        n = [int(self.p["n"][k]) for k in range(d)]
+        sizes = []
+        for k in range(d):
+            e = list(n)
+            e[k] += 1
+            sizes.append(tuple(reversed(e)))
+        tot = sum((5 * nv + 1) * int(np.prod(s)) for s in sizes)
+        rec = np.zeros(tot)
+        dJU = np.zeros((nv,) + self.shape)
+        dJ = np.zeros(self.shape)
+        self.L.orc_rhs_record(self._cp(), _p(_arr(JU)), _p(_arr(J)), _p(_arr(met)),
+                              _p(None if xit is None else _arr(xit)), _p(dJU), _p(dJ), _p(rec))
+        out, o = [], 0
+        for s in sizes:
+            m = int(np.prod(s))
+            r = rec[o:o + (5 * nv + 1) * m].reshape((5 * nv + 1,) + s)
+            o += (5 * nv + 1) * m
+            out.append(dict(F=r[:nv], gcl=r[nv], Y=r[nv + 1:2 * nv + 1], jw=r[2 * nv + 1:3 * nv + 1],
+                            j0=r[3 * nv + 1:4 * nv + 1], scale=r[4 * nv + 1:5 * nv + 1]))
+        return out, dJU, dJ
+
+    def interface_flux(self, st, mx, mt):
+        """One interface from its 6-node stencil: st (6, nv) conserved states of nodes i-2..i+3,
+        mx (6, d) their J xi_k/x_j, mt (6,) their J xi_k/t.  Returns dict(F, gcl, prod, Y, jw, j0,
+        scale)."""
+        nv = self.nv
+        F = np.zeros(nv)
+        g, pr = np.zeros(1), np.zeros(1)
+        dg = np.zeros(4 * nv)
+        self.L.orc_interface_flux(self._cp(), _p(_arr(st, 6 * nv)), _p(_arr(mx, 6 * self.d)), _p(_arr(mt, 6)),
+                                  _p(F), _p(g), _p(pr), _p(dg))
+        dg = dg.reshape(4, nv)
+        return dict(F=F, gcl=g[0], prod=pr[0], Y=dg[0], jw=dg[1], j0=dg[2], scale=dg[3])
 
     def rk_stage(self, s, dt, JU0, J0, JUs, Js, xn, xdot=None):
         JUo = np.zeros((self.nv,) + self.shape)

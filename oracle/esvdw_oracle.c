@@ -713,9 +713,12 @@ void orc_uniform_mesh(const orc_cfg *c, double *x) {
 /* One interface i+1/2 in direction k.  st[s] (s = 0..5 <-> nodes i-2..i+3) hold the
  * conserved state, mx[s][j] = J xi_k/x_j and mt[s] = J xi_k/t of those nodes.
  * Outputs the entropy-stable flux Fes[nv] and the GCL flux of J xi_k/t.  Returns the
- * interface entropy production sum_m [W_m] Y_m [W_m]^WENO * Lambda / 2 in *prod. */
+ * interface entropy production sum_m [W_m] Y_m [W_m]^WENO * Lambda / 2 in *prod.
+ * diag (may be NULL; 4 NVMAX doubles) receives, per component m, the sign-matrix entry Y_m,
+ * the reconstructed jump [W_m]^WENO, the plain jump [W_m] before the zero test and the
+ * rounding scale of W_m used by that test (for tests of the dissipation's switch). */
 static void interface_flux(const orc_cfg *c, double st[6][NVMAX], double mx[6][3], const double *mt,
-                           double *Fes, double *gclt, double *prod) {
+                           double *Fes, double *gclt, double *prod, double *diag) {
   int d = c->dim, nv = d + 2;
   /* eq. ECFlux_curv_2p and eq. GCL_flux with w = 3; node offset o <-> index i + o - 2 */
   double Fec[NVMAX] = {0}, gt = 0.0;
@@ -730,6 +733,8 @@ static void interface_flux(const orc_cfg *c, double st[6][NVMAX], double mx[6][3
   *gclt = gt;
   for (int q = 0; q < nv; ++q) Fes[q] = Fec[q];
   *prod = 0.0;
+  if (diag)
+    for (int q = 0; q < 4 * NVMAX; ++q) diag[q] = 0.0;
   if (!c->dissipation) return;
 
   /* averaged state at i+1/2: rho = L(rho), v = {v}, p = L(rho)/L(rho/p) */
@@ -797,9 +802,15 @@ static void interface_flux(const orc_cfg *c, double st[6][NVMAX], double mx[6][3
     double Wp = orc_mrweno5(c, W[5][r], W[4][r], W[3][r], W[2][r], W[1][r]);
     double jw = Wp - Wm;
     double j0 = W[3][r] - W[2][r];
+    if (diag) {
+      diag[NVMAX + r] = jw;
+      diag[2 * NVMAX + r] = j0;
+      diag[3 * NVMAX + r] = Wmag[2][r] + Wmag[3][r];
+    }
     if (fabs(j0) <= ldexp(Wmag[2][r] + Wmag[3][r], -40)) j0 = 0.0;
     int same = (jw > 0.0 && j0 > 0.0) || (jw < 0.0 && j0 < 0.0);
     YdW[r] = same ? jw : 0.0;
+    if (diag) diag[r] = same ? 1.0 : 0.0;
     *prod += 0.5 * Lam * j0 * YdW[r];
   }
   /* F_es = F_ec - 1/2 Lambda T^{-1} R Y [W]^WENO, with T^{-1} = T^T */
@@ -821,14 +832,19 @@ static void interface_flux(const orc_cfg *c, double st[6][NVMAX], double mx[6][3
  * it receives, per node, the entropy production of the two faces' share (sum over
  * the domain gives the total dissipation). */
 static void rhs_padded(const orc_cfg *c, const pad_t *pm, double *const *Up, const double *metp,
-                       const double *xitp, double *dJU, double *dJ, double *prodsum) {
+                       const double *xitp, double *dJU, double *dJ, double *prodsum, double *rec) {
   int d = c->dim, nv = d + 2;
   long N = nodes(c);
   for (long q = 0; q < N * nv; ++q) dJU[q] = 0.0;
   for (long q = 0; q < N; ++q) dJ[q] = 0.0;
   double psum = 0.0;
+  const int NR = 5 * nv + 1; /* fields of one interface record (see orc_rhs_record) */
+  long roff = 0;             /* start of direction k's records */
   for (int k = 0; k < d; ++k) {
     double dk = dxi(c, k);
+    int e[3] = {pm->n[0], pm->n[1], pm->n[2]};
+    e[k] += 1;
+    long nif = (long)e[0] * e[1] * e[2];
     double cellvol = 1.0;
     for (int q = 0; q < d; ++q) cellvol *= dxi(c, q);
     int lo[3] = {0, 0, 0}, hi[3] = {pm->n[0], pm->n[1], pm->n[2]};
@@ -845,9 +861,20 @@ static void rhs_padded(const orc_cfg *c, const pad_t *pm, double *const *Up, con
             for (int j = 0; j < d; ++j) mx[s][j] = metp[(k * d + j) * pm->N + qp];
             mt[s] = xitp[k * pm->N + qp];
           }
-          double Fes[NVMAX], gt, prod;
-          interface_flux(c, st, mx, mt, Fes, &gt, &prod);
+          double Fes[NVMAX], gt, prod, dg[4 * NVMAX];
+          interface_flux(c, st, mx, mt, Fes, &gt, &prod, rec ? dg : NULL);
           int ii[3] = {i0, i1, i2};
+          if (rec) {
+            int a[3] = {i0, i1, i2};
+            a[k] += 1;
+            long ti = ((long)a[2] * e[1] + a[1]) * e[0] + a[0];
+            double *r = rec + roff;
+            for (int v = 0; v < nv; ++v) {
+              r[(long)v * nif + ti] = Fes[v];
+              for (int q = 0; q < 4; ++q) r[(long)(nv + 1 + q * nv + v) * nif + ti] = dg[q * NVMAX + v];
+            }
+            r[(long)nv * nif + ti] = gt;
+          }
           /* the interface contributes -F/dxi to node i and +F/dxi to node i+1 */
           if (ii[k] >= 0) {
             long qi = iidx(c, ii[0], ii[1], ii[2]);
@@ -864,6 +891,7 @@ static void rhs_padded(const orc_cfg *c, const pad_t *pm, double *const *Up, con
           /* count each interior-domain face once: the i+1/2 faces for i = 0..n-1 */
           if (ii[k] >= 0) psum += prod * cellvol / dk;
         }
+    roff += (long)NR * nif;
   }
   if (prodsum) *prodsum = psum;
 }
@@ -946,11 +974,51 @@ void orc_rhs(const orc_cfg *c, const double *JU, const double *J, const double *
   double *xz = NULL;
   if (!xit) xz = calloc((long)d * N, sizeof(double));
   pad_metrics(c, &pm, met, xit ? xit : xz, metp, xitp);
-  rhs_padded(c, &pm, Up, metp, xitp, dJU, dJ, prod);
+  rhs_padded(c, &pm, Up, metp, xitp, dJU, dJ, prod, NULL);
   free(xz);
   free(metp);
   free(xitp);
   free_fields(Up, nv);
+}
+
+/* The interface records behind orc_rhs, for tests of single interfaces: per direction k, in
+ * order, (5 nv + 1) fields over the interfaces of k (e_k = n_k + 1 along k, index
+ * (a2 e1 + a1) e0 + a0 with a_k - 1 the left node): the entropy-stable flux (nv), the GCL flux
+ * of J xi_k/t (1), then per component Y_m (nv), [W_m]^WENO (nv), the plain jump [W_m] before
+ * its zero test (nv) and that test's rounding scale (nv).  dJU, dJ as orc_rhs. */
+void orc_rhs_record(const orc_cfg *c, const double *JU, const double *J, const double *met, const double *xit,
+                    double *dJU, double *dJ, double *rec) {
+  int d = c->dim, nv = d + 2;
+  long N = nodes(c);
+  pad_t pm = make_pad(c, GS);
+  double **Up = pad_state(c, &pm, JU, J);
+  double *metp = calloc((long)d * d * pm.N, sizeof(double));
+  double *xitp = calloc((long)d * pm.N, sizeof(double));
+  double *xz = NULL;
+  if (!xit) xz = calloc((long)d * N, sizeof(double));
+  pad_metrics(c, &pm, met, xit ? xit : xz, metp, xitp);
+  rhs_padded(c, &pm, Up, metp, xitp, dJU, dJ, NULL, rec);
+  free(xz);
+  free(metp);
+  free(xitp);
+  free_fields(Up, nv);
+}
+
+/* One interface from explicit stencil data (tests): st[6 * nv] conserved states of nodes
+ * i-2..i+3, mx[6 * d] their J xi_k/x_j, mt[6] their J xi_k/t.  Outputs as interface_flux;
+ * diag (may be NULL) receives 4 nv values: Y, [W]^WENO, plain [W], rounding scale. */
+void orc_interface_flux(const orc_cfg *c, const double *st, const double *mx, const double *mt, double *Fes,
+                        double *gclt, double *prod, double *diag) {
+  int d = c->dim, nv = d + 2;
+  double S[6][NVMAX], M[6][3], dg[4 * NVMAX];
+  for (int s = 0; s < 6; ++s) {
+    for (int v = 0; v < nv; ++v) S[s][v] = st[s * nv + v];
+    for (int j = 0; j < 3; ++j) M[s][j] = j < d ? mx[s * d + j] : 0.0;
+  }
+  interface_flux(c, S, M, mt, Fes, gclt, prod, dg);
+  if (diag)
+    for (int q = 0; q < 4; ++q)
+      for (int v = 0; v < nv; ++v) diag[q * nv + v] = dg[q * NVMAX + v];
 }
 
 /* RHS on the stage mesh xs (metrics from the GM-padded mesh, including ghosts) */
@@ -976,7 +1044,7 @@ static void rhs_on_mesh(const orc_cfg *c, const double *JU, const double *J, con
         }
   }
   double **Up = pad_state(c, &pm, JU, J);
-  rhs_padded(c, &pm, Up, metp, xitp, dJU, dJ, NULL);
+  rhs_padded(c, &pm, Up, metp, xitp, dJU, dJ, NULL, NULL);
   free_fields(Up, nv);
   free(metp);
   free(xitp);
