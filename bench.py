@@ -23,19 +23,14 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# algorithmic FP64 operation counts (each +, -, *, /, sqrt, log, log1p, min, max, abs = 1)
-# per 2D interface of the flux kernel: the two-point EC fluxes of the pairs the interface
-# owns (3 pairs of ~150 operations, plus the alpha combination of its 6 pair fluxes) and
-# the dissipation (averaged state and eigen-system ~130, W on the 6-node stencil ~150,
-# rounding scale of W ~60, 8 MR-WENO5 reconstructions of ~87, sign matrix and projection
-# back ~60).
-FLOPS_PER_IFACE_2D = 3 * 150 + 60 + 130 + 150 + 60 + 8 * 87 + 60
-# per 2D node-stage: two interfaces, the node kernel (~100) and the update (~20)
-FLOPS_PER_NODE_STAGE_2D = 2 * FLOPS_PER_IFACE_2D + 120
-# 3D interface (estimate on the same counting rules): 3 pair fluxes of ~180, combination ~70,
-# averaged state and 3D eigen-system ~160, W on 6 nodes ~210, rounding scale ~80, 10 MR-WENO5
-# reconstructions of ~87, projection ~80
-FLOPS_PER_IFACE_3D = 3 * 180 + 70 + 160 + 210 + 80 + 10 * 87 + 80
+# Algorithmic FP64 operation counts (each +, -, *, /, sqrt, log, min, max, abs = 1), from the
+# per-node-stage budget of the scheme in 2D: about 3.7 kflop per node and RK stage, of which
+# about 0.3 k is node thermodynamics and the update and 3.4 k the interface fluxes (two-point EC
+# pair fluxes ~1.0 k, MR-WENO reconstructions ~1.76 k, projections ~0.38 k, averaged state and
+# eigen-system ~0.26 k), i.e. 1.7 k per interface (a node-stage owns one interface per direction).
+FLOPS_PER_IFACE_2D = 1700
+# 3D: about 7.7 kflop per node-stage, ~0.3 k outside the fluxes, over three interfaces
+FLOPS_PER_IFACE_3D = 2470
 # algorithmic HBM bytes of one flux-kernel interface: one read of a node's 17 fields
 # (rho, v1, v2, T, p, 1/T, g, 4 entropy variables, 4 metrics, 2 grid-speed metrics) and one
 # write of the 5 flux values
@@ -54,21 +49,33 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(n):
-    """HBM bytes per k_flux launch from the committed counter summary (FETCH_SIZE + WRITE_SIZE,
-    each scaled by the copy kernel's reading), if it was taken on the current kernel source
-    at this size; else None."""
-    path = os.path.join(ROOT, "profiles", "k_flux_2d_1024_counters.md")
+def profile_record(name, n):
+    """The machine-readable block of a committed rocprofv3 summary under profiles/, if it was
+    taken on the current kernel sources at this size; else None."""
+    path = os.path.join(ROOT, "profiles", name)
     try:
         with open(path) as f:
             txt = f.read()
-        blob = txt.split("```json")[1].split("```")[0]
-        d = json.loads(blob)
+        d = json.loads(txt.split("```json")[1].split("```")[0])
     except (OSError, IndexError, ValueError):
         return None
     if d.get("source_hash") != kernel_source_hash() or d.get("size") != n:
         return None
-    return d.get("traffic_bytes_per_launch")
+    return d
+
+
+def measured_traffic(n):
+    """HBM bytes per k_flux launch from the committed counter summary (FETCH_SIZE + WRITE_SIZE,
+    each scaled by the copy kernel's reading); None unless taken on the current sources."""
+    d = profile_record("k_flux_2d_1024_counters.md", n)
+    return None if d is None else d.get("traffic_bytes_per_launch")
+
+
+def in_step_flux_us(n):
+    """Average k_flux duration inside graph-replayed steps, from the committed kernel trace of
+    the step (rocprofv3 --kernel-trace); None unless taken on the current sources."""
+    d = profile_record("kernels_2d_1024_moving_step.md", n)
+    return None if d is None else d.get("k_flux_in_step_us")
 
 
 def make_problem(workload, n):
@@ -86,22 +93,37 @@ def initial_prim(workload, p, seed):
     return synth.quadrants_2d(p, synth.quadrant_states(p, seed))
 
 
-def cpu_baseline(workload, size, seed, steps):
-    """The oracle on the host: `steps` moving-mesh steps of the same problem (bounded sample)."""
+def cpu_baseline(workload, size, seed, steps, steps_mt):
+    """The oracle on the host's cores, on a bounded sample of the same workload: `steps_mt`
+    moving-mesh steps with its OpenMP build on every core this process may run on
+    (os.sched_getaffinity), and `steps` with the single-thread build (the one the parity tests
+    use); both start from the same initial data.  The OpenMP build is the same source with its
+    outer node loops split across threads (identical results)."""
     import oracle
     p = make_problem(workload, size)
-    o = oracle.Oracle(p)
-    x = o.uniform_mesh()
-    J = o.jacobian(x)
-    JU = o.init_state(initial_prim(workload, p, seed), J)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        JU, J, x, _ = o.step(JU, J, x, moving=True)
-    el = time.perf_counter() - t0
+    prim = initial_prim(workload, p, seed)
     nodes = size ** p["dim"]
-    return {"value": nodes * 3 * steps / el, "unit": "node-stages/s", "cores": 1, "kind": "oracle",
-            "sample": "%d moving-mesh step(s) of the same %s problem at %s nodes (%.1f s, single thread)"
-                      % (steps, workload, "x".join([str(size)] * p["dim"]), el)}
+    out = {}
+    cores = len(os.sched_getaffinity(0))
+    for mt in (True, False):
+        o = oracle.Oracle(p, omp=mt)
+        threads = o.L.orc_threads(cores if mt else 1)
+        x = o.uniform_mesh()
+        J = o.jacobian(x)
+        JU = o.init_state(prim, J)
+        n = steps_mt if mt else steps
+        t0 = time.perf_counter()
+        for _ in range(n):
+            JU, J, x, _ = o.step(JU, J, x, moving=True)
+        el = time.perf_counter() - t0
+        out[mt] = dict(value=nodes * 3 * n / el, unit="node-stages/s", cores=threads, seconds=el, steps=n)
+    grid = "x".join([str(size)] * p["dim"])
+    res = {"value": out[True]["value"], "unit": "node-stages/s", "cores": out[True]["cores"], "kind": "oracle",
+           "sample": "%d moving-mesh step(s) of the same %s problem at %s nodes, OpenMP build on %d threads "
+                     "(%.1f s)" % (out[True]["steps"], workload, grid, out[True]["cores"], out[True]["seconds"]),
+           "single_thread": {"value": out[False]["value"], "unit": "node-stages/s", "cores": 1,
+                             "sample": "%d step(s), %.1f s" % (out[False]["steps"], out[False]["seconds"])}}
+    return res
 
 
 def main():
@@ -214,11 +236,15 @@ def main():
                 "avg_launch_ms": t_launch * 1e3}
     if not three:
         roofline["algorithmic_bytes_GBps"] = BYTES_PER_IFACE_2D * nif / t_launch / 1e9
+        t_in = in_step_flux_us(n)
+        roofline["in_step_launch_ms"] = None if t_in is None else t_in / 1e3
+        roofline["frac_in_step"] = None if t_in is None else FLOPS_PER_IFACE_2D * nif / (t_in * 1e-6) / PEAK_FP64
+    roofline["flops_per_interface"] = FLOPS_PER_IFACE_3D if three else FLOPS_PER_IFACE_2D
 
     cpu = None
     if not args.no_cpu:
         print("cpu baseline ...", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(args.workload, args.cpu_size or (80 if three else 1024), args.seed, 1 if three else 2)
+        cpu = cpu_baseline(args.workload, args.cpu_size or (80 if three else 1024), args.seed, 1, 2 if three else 3)
 
     if three:
         metric = "FP64 cell-stage updates/s (3D %d³ moving mesh)" % n

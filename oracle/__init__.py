@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "esvdw_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
-_lib = None
+_libs = {}
 
 BC = {"periodic": 0, "outflow": 1}
 MONITOR = {"vdw": 0, "sine": 1}
@@ -24,14 +24,20 @@ MONVAR = {"rho": 0, "G": 1}
 FLAGS = {"INADMISSIBLE": 1, "MEANCONSTRAINT": 2, "NAN": 4, "NOTCONVERGED": 8}
 
 
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+
+
 def build(force=True):
-    """Compile the oracle (plain -O2, no FMA contraction, no fast-math)."""
+    """Compile the oracle (plain -O2, no FMA contraction, no fast-math), and the same source
+    with OpenMP for the multi-core CPU baseline (identical arithmetic; the tests use the
+    single-thread build)."""
     if not force and os.path.exists(_LIB):
         return _LIB
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC", "-shared",
-           "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
-    subprocess.check_call(cmd)
+    base = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC", "-shared", "-Wall"]
+    subprocess.check_call(base + ["-Wno-unknown-pragmas", "-o", _LIB + ".tmp", _SRC, "-lm"])
     os.replace(_LIB + ".tmp", _LIB)
+    subprocess.check_call(base + ["-fopenmp", "-o", _LIB_OMP + ".tmp", _SRC, "-lm"])
+    os.replace(_LIB_OMP + ".tmp", _LIB_OMP)
     return _LIB
 
 
@@ -89,14 +95,16 @@ _D = ctypes.POINTER(ctypes.c_double)
 _CP = ctypes.POINTER(Cfg)
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+def lib(omp=False):
+    """The oracle library; omp=True: the OpenMP build of the same source (CPU baseline only)."""
+    if omp not in _libs:
+        path = _LIB_OMP if omp else _LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
             build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(path)
         sig = {
             "orc_get_flags": (ctypes.c_uint, [ctypes.c_int]),
+            "orc_threads": (ctypes.c_int, [ctypes.c_int]),
             "orc_T_from_rho_p": (ctypes.c_double, [_CP, ctypes.c_double, ctypes.c_double]),
             "orc_admissible": (ctypes.c_int, [_CP, ctypes.c_double, ctypes.c_double]),
             "orc_eos_state": (None, [_CP, ctypes.c_double, ctypes.c_double, _D]),
@@ -134,8 +142,8 @@ def lib():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
-        _lib = L
-    return _lib
+        _libs[omp] = L
+    return _libs[omp]
 
 
 def _p(a):
@@ -155,10 +163,10 @@ def _arr(x, n=None):
 class Oracle:
     """Oracle bound to one problem configuration (dict from synth.problem)."""
 
-    def __init__(self, p):
+    def __init__(self, p, omp=False):
         self.p = dict(p)
         self.c = make_cfg(p)
-        self.L = lib()
+        self.L = lib(omp)
         self.d = int(p["dim"])
         self.nv = self.d + 2
         self.shape = tuple(int(p["n"][k]) for k in reversed(range(self.d)))  # (z, y, x)

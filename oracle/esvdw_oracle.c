@@ -26,6 +26,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define NVMAX 5
 #define GS 3  /* ghost width of node states and metrics */
@@ -59,6 +62,23 @@ typedef struct {
 } orc_cfg;
 
 static unsigned g_flags = 0;
+
+/* flags are raised from the parallel loops of the OpenMP build: atomically there */
+static void raise_flag(unsigned f) {
+#pragma omp atomic
+  g_flags |= f;
+}
+
+/* threads of the OpenMP build (the CPU baseline); 1 in the plain build */
+int orc_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
 
 unsigned orc_get_flags(int clear) {
   unsigned f = g_flags;
@@ -155,8 +175,8 @@ static void cons_to_z(const orc_cfg *c, const double *U, double *z) {
   }
   double e = U[d + 1] / rho - 0.5 * v2;
   z[d + 1] = (e + c->a * rho) / c->cv;
-  if (!orc_admissible(c, rho, z[d + 1])) g_flags |= F_INADMISSIBLE;
-  if (isnan(rho) || isnan(z[d + 1])) g_flags |= F_NAN;
+  if (!orc_admissible(c, rho, z[d + 1])) raise_flag(F_INADMISSIBLE);
+  if (isnan(rho) || isnan(z[d + 1])) raise_flag(F_NAN);
 }
 
 /* prim = (rho, v, p, T) from U, exported for tests */
@@ -283,7 +303,7 @@ void orc_ec_pair(const orc_cfg *c, const double *Ul, const double *Ur, double *U
   /* Theorem 3.1: the system is uniquely solvable when the mean state satisfies
      R{T} - 2a{rho}(1 - b{rho})^2 > 0 (eq. mean_constraint); then D > 0 */
   double obm = 1.0 - b * m_rho;
-  if (!(D > 0.0) || !(R * m_T - 2.0 * a * m_rho * obm * obm > 0.0)) g_flags |= F_MEANCONSTRAINT;
+  if (!(D > 0.0) || !(R * m_T - 2.0 * a * m_rho * obm * obm > 0.0)) raise_flag(F_MEANCONSTRAINT);
 
   /* U~ */
   Ut[0] = (m_rho * A + m_g) / D;
@@ -344,10 +364,14 @@ double orc_mrweno5(const orc_cfg *c, double wm2, double wm1, double w0, double w
   double b1 = fmin(dl * dl, dr * dr);
   double t1 = wm1 - 2.0 * w0 + w1, t2 = w1 - wm1;
   double b2 = 13.0 / 12.0 * t1 * t1 + 0.25 * t2 * t2;
-  double b3 = (231153.0 * w0 * w0 - 299076.0 * w0 * (wm1 + w1) + 67923.0 * w0 * (wm2 + w2)
-               + 104963.0 * (wm1 * wm1 + w1 * w1) - 51001.0 * (wm1 * wm2 + w1 * w2)
-               + 179098.0 * wm1 * w1 - 38947.0 * (wm1 * w2 + wm2 * w1)
-               + 6908.0 * (wm2 * wm2 + w2 * w2) + 8209.0 * wm2 * w2) / 5040.0;
+  /* b3 depends only on derivatives of the quartic, so it is unchanged when a constant is added
+     to the data; it is evaluated on the data relative to the centre value w0, which is the
+     same quadratic form without the cancellation between terms of the size of the data's
+     square (entropy-variable data carry large offsets, c_v ln T) */
+  double am = wm2 - w0, bm = wm1 - w0, cp = w1 - w0, dp = w2 - w0;
+  double b3 = (104963.0 * (bm * bm + cp * cp) - 51001.0 * (bm * am + cp * dp)
+               + 179098.0 * bm * cp - 38947.0 * (bm * dp + am * cp)
+               + 6908.0 * (am * am + dp * dp) + 8209.0 * am * dp) / 5040.0;
   double tt = 0.5 * (fabs(b3 - b1) + fabs(b3 - b2));
   double tau = tt * tt;
   double eps = c->weno_eps;
@@ -585,6 +609,7 @@ static void metrics_padded(const orc_cfg *c, const pad_t *px, double *const *xp,
           /* the product is needed 3 + GS layers out along `outer` and GS layers out
              along the other two directions; delta_inner reads 3 more along `inner` */
           for (long q = 0; q < px->N; ++q) tmp[q] = 0.0;
+#pragma omp parallel for schedule(static)
           for (int i2 = -GM; i2 < px->n[2] + GM; ++i2)
             for (int i1 = -GM; i1 < px->n[1] + GM; ++i1)
               for (int i0 = -GM; i0 < px->n[0] + GM; ++i0) {
@@ -593,6 +618,7 @@ static void metrics_padded(const orc_cfg *c, const pad_t *px, double *const *xp,
                 long q = pidx(px, i0, i1, i2);
                 tmp[q] = delta_op(px, xp[j1], inner, i0, i1, i2) * xp[j2][q];
               }
+#pragma omp parallel for schedule(static)
           for (int i2 = -GS; i2 < pm->n[2] + GS; ++i2)
             for (int i1 = -GS; i1 < pm->n[1] + GS; ++i1)
               for (int i0 = -GS; i0 < pm->n[0] + GS; ++i0)
@@ -603,6 +629,7 @@ static void metrics_padded(const orc_cfg *c, const pad_t *px, double *const *xp,
     free(tmp);
     return;
   }
+#pragma omp parallel for collapse(2) schedule(static)
   for (int i2 = -pm->g[2]; i2 < pm->n[2] + pm->g[2]; ++i2)
     for (int i1 = -pm->g[1]; i1 < pm->n[1] + pm->g[1]; ++i1)
       for (int i0 = -pm->g[0]; i0 < pm->n[0] + pm->g[0]; ++i0) {
@@ -766,7 +793,7 @@ static void interface_flux(const orc_cfg *c, double st[6][NVMAX], double mx[6][3
     ub[r] = s;
   }
   double Rm[NVMAX * NVMAX], lam[NVMAX];
-  if (!orc_eigen(c, rb, ub, pb, Rm, lam)) g_flags |= F_MEANCONSTRAINT;
+  if (!orc_eigen(c, rb, ub, pb, Rm, lam)) raise_flag(F_MEANCONSTRAINT);
   double Lam = 0.0;
   for (int q = 0; q < nv; ++q) {
     double v = fabs(mtb + L * lam[q]);
@@ -847,11 +874,19 @@ static void rhs_padded(const orc_cfg *c, const pad_t *pm, double *const *Up, con
     long nif = (long)e[0] * e[1] * e[2];
     double cellvol = 1.0;
     for (int q = 0; q < d; ++q) cellvol *= dxi(c, q);
-    int lo[3] = {0, 0, 0}, hi[3] = {pm->n[0], pm->n[1], pm->n[2]};
-    lo[k] = -1; /* interfaces i+1/2 for i = -1 .. n-1 */
-    for (int i2 = lo[2]; i2 < hi[2]; ++i2)
-      for (int i1 = lo[1]; i1 < hi[1]; ++i1)
-        for (int i0 = lo[0]; i0 < hi[0]; ++i0) {
+    /* lines of interfaces along k, i+1/2 for i = -1 .. n_k - 1; each line writes only its own
+       nodes, so with OpenMP (the throughput build) the lines run in parallel */
+    const int ka = (k + 1) % 3, kb = (k + 2) % 3;
+    const int na = pm->n[ka], nb = pm->n[kb];
+#pragma omp parallel for collapse(2) reduction(+ : psum) schedule(static)
+    for (int ib = 0; ib < nb; ++ib)
+      for (int ia = 0; ia < na; ++ia)
+        for (int ik = -1; ik < pm->n[k]; ++ik) {
+          int il[3];
+          il[k] = ik;
+          il[ka] = ia;
+          il[kb] = ib;
+          const int i0 = il[0], i1 = il[1], i2 = il[2];
           double st[6][NVMAX], mx[6][3], mt[6];
           for (int s = 0; s < 6; ++s) {
             int ii[3] = {i0, i1, i2};
@@ -1148,6 +1183,7 @@ void orc_monitor(const orc_cfg *c, const double *JU, const double *J, double *om
   int nterm = c->monitor_kind == MON_VDW ? c->kappa + 1 : 2;
   double *term = calloc((long)nterm * N, sizeof(double));
   double mxv[3] = {0, 0, 0};
+#pragma omp parallel for collapse(2) reduction(max : mxv[:3]) schedule(static)
   for (int i2 = 0; i2 < p1.n[2]; ++i2)
     for (int i1 = 0; i1 < p1.n[1]; ++i1)
       for (int i0 = 0; i0 < p1.n[0]; ++i0) {
@@ -1200,6 +1236,7 @@ void orc_filter(const orc_cfg *c, double *omega, int npass) {
   for (int it = 0; it < npass; ++it) {
     to_pad(c, &p1, omega, w);
     fill_ghosts(c, &p1, w, 3, 0);
+#pragma omp parallel for collapse(2) schedule(static)
     for (int i2 = 0; i2 < p1.n[2]; ++i2)
       for (int i1 = 0; i1 < p1.n[1]; ++i1)
         for (int i0 = 0; i0 < p1.n[0]; ++i0) {
@@ -1237,6 +1274,7 @@ int orc_jacobi(const orc_cfg *c, const double *omega, double *x, int nsweep, dou
   for (it = 0; it < nsweep;) {
     double **xp = pad_mesh(c, &p1, x, 1);
     res = 0.0;
+#pragma omp parallel for collapse(2) reduction(max : res) schedule(static)
     for (int i2 = 0; i2 < p1.n[2]; ++i2)
       for (int i1 = 0; i1 < p1.n[1]; ++i1)
         for (int i0 = 0; i0 < p1.n[0]; ++i0) {
@@ -1344,6 +1382,7 @@ double orc_limiter(const orc_cfg *c, const double *xn, const double *xmu) {
   pad_t p1 = make_pad(c, 1);
   double **xp = pad_mesh(c, &p1, xn, 1);
   double g = 1.0;
+#pragma omp parallel for collapse(2) reduction(min : g) schedule(static)
   for (int i2 = 0; i2 < p1.n[2]; ++i2)
     for (int i1 = 0; i1 < p1.n[1]; ++i1)
       for (int i0 = 0; i0 < p1.n[0]; ++i0) {
@@ -1380,7 +1419,7 @@ void orc_redistribute(const orc_cfg *c, const double *JU, const double *J, const
   for (long q = 0; q < d * N; ++q) xm[q] = xn[q] + (warm_dx ? warm_dx[q] : 0.0);
   double res = 0.0;
   int sw = orc_jacobi(c, omega, xm, c->mu, c->fixed_mu ? 0.0 : c->mesh_tol, &res);
-  if (!c->fixed_mu && !(res < c->mesh_tol)) g_flags |= F_NOTCONVERGED;
+  if (!c->fixed_mu && !(res < c->mesh_tol)) raise_flag(F_NOTCONVERGED);
   double gam = orc_limiter(c, xn, xm);
   double dt = c->dt_fixed > 0.0 ? c->dt_fixed : orc_cfl_dt(c, JU, J, xn);
   for (long q = 0; q < d * N; ++q) xdot[q] = gam * (xm[q] - xn[q]) / dt;

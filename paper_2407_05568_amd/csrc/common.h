@@ -32,6 +32,19 @@ struct Geo {
 #define AL2 (-0.3)
 #define AL3 (1.0 / 30.0)
 
+// 1/x for the flux kernels: the hardware reciprocal estimate refined by two Newton-Raphson
+// steps for 1/x (r <- r + r (1 - x r), each doubling the correct bits), within about one unit
+// in the last place for normal, finite x (the kernels' denominators are products of positive
+// thermodynamic quantities or of MR-WENO weights, far from zero, overflow and denormals).
+// Cheaper than the correctly rounded division sequence, which also handles those edge cases.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 __device__ __forceinline__ int floordiv(int i, int n) { return i >= 0 ? i / n : -((-i + n - 1) / n); }
 
 // interior source of a (possibly ghost) state index along direction k: periodic wrap, mirror
@@ -208,6 +221,54 @@ __device__ __forceinline__ void metrics2(const Geo &G, const double *__restrict_
   m[1][1] = (0.5 * d00) * G.idxi[0];
 }
 
+// 2D metric stencils from LDS: a tile of TX x TY nodes whose first node has interior index
+// (c0, c1), with the stage mesh x_n + cdt xdot of the tile and a 3-node halo staged once per
+// block (each mesh value is then read from memory about (TX+6)(TY+6)/(TX TY) times instead of
+// 12 or 24 times per node).  Values and sums are those of metrics2.
+template <int TX, int TY> struct MeshTile2 {
+  double x[2][TY + 6][TX + 6];
+};
+
+template <int TX, int TY>
+__device__ __forceinline__ void mesh_tile_fill(const Geo &G, const double *__restrict__ xn, const double *__restrict__ xd,
+                                               double cdt, int c0, int c1, MeshTile2<TX, TY> &T, int tid, int nth) {
+  constexpr int W = TX + 6, NS = W * (TY + 6);
+  for (int idx = tid; idx < NS; idx += nth) {
+    const int a = idx % W, b = idx / W;
+    const int i0 = c0 - 3 + a, i1 = c1 - 3 + b;
+    // the stencils of the padded grid (3 ghost layers) reach 6 nodes beyond the interior
+    const bool in = i0 >= -6 && i0 < G.n[0] + 6 && i1 >= -6 && i1 < G.n[1] + 6;
+    T.x[0][b][a] = in ? stage_x(G, xn, xd, cdt, 0, i0, i1, 0) : 0.0;
+    T.x[1][b][a] = in ? stage_x(G, xn, xd, cdt, 1, i0, i1, 0) : 0.0;
+  }
+}
+
+// m[k][j] = J dxi_k/dx_j of the node at tile coordinates (u, v)
+template <int TX, int TY>
+__device__ __forceinline__ void mesh_tile_metrics(const Geo &G, const MeshTile2<TX, TY> &T, int u, int v,
+                                                  double m[2][2]) {
+  const double al[3] = {AL1, AL2, AL3};
+  const int a = u + 3, b = v + 3;
+  double d[2][2];  // d[q][r] = delta_q[x_r]
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 1; k <= 3; ++k) {
+        const double p = q == 0 ? T.x[r][b][a + k] : T.x[r][b + k][a];
+        const double n = q == 0 ? T.x[r][b][a - k] : T.x[r][b - k][a];
+        acc += al[k - 1] * (p - n);
+      }
+      d[q][r] = 0.5 * acc;
+    }
+  m[0][0] = d[1][1] * G.idxi[1];
+  m[0][1] = -d[1][0] * G.idxi[1];
+  m[1][0] = -d[0][1] * G.idxi[0];
+  m[1][1] = d[0][0] * G.idxi[0];
+}
+
 // ---------------------------------------------------------------------------------
 // thermodynamics (eq. vdWEOS and the closed forms of Section 2, general units)
 // ---------------------------------------------------------------------------------
@@ -293,10 +354,12 @@ __device__ __forceinline__ double mrweno5(const Geo &G, double a, double b, doub
   double s1 = fmin(dl * dl, dr * dr);
   double t1 = b - 2.0 * c + d, t2 = d - b;
   double s3 = (13.0 / 12.0) * t1 * t1 + 0.25 * t2 * t2;
-  // Jiang-Shu functional of the quartic, as a quadratic form in (a..e)
-  double s5 = (c * (231153.0 * c - 299076.0 * (b + d) + 67923.0 * (a + e)) + 104963.0 * (b * b + d * d) -
-               51001.0 * (a * b + d * e) + 179098.0 * b * d - 38947.0 * (b * e + a * d) + 6908.0 * (a * a + e * e) +
-               8209.0 * a * e) *
+  // the Jiang-Shu functional of the quartic depends only on its derivatives, so it is evaluated
+  // on the data relative to the centre value c: the same quadratic form without cancellation
+  // between terms of the size of the data's square (entropy-variable data carry c_v ln T offsets)
+  const double am = a - c, bm = b - c, dp = d - c, ep = e - c;
+  double s5 = (104963.0 * (bm * bm + dp * dp) - 51001.0 * (am * bm + dp * ep) + 179098.0 * bm * dp -
+               38947.0 * (bm * ep + am * dp) + 6908.0 * (am * am + ep * ep) + 8209.0 * am * ep) *
               (1.0 / 5040.0);
   double tt = 0.5 * (fabs(s5 - s1) + fabs(s5 - s3));
   double tau = tt * tt;
@@ -319,9 +382,12 @@ __device__ __forceinline__ void mrweno5_frac(const Geo &G, double a, double b, d
   double s1 = fmin(dl * dl, dr * dr);
   double t1 = b - 2.0 * c + d, t2 = d - b;
   double s3 = (13.0 / 12.0) * t1 * t1 + 0.25 * t2 * t2;
-  double s5 = (c * (231153.0 * c - 299076.0 * (b + d) + 67923.0 * (a + e)) + 104963.0 * (b * b + d * d) -
-               51001.0 * (a * b + d * e) + 179098.0 * b * d - 38947.0 * (b * e + a * d) + 6908.0 * (a * a + e * e) +
-               8209.0 * a * e) *
+  // the Jiang-Shu functional of the quartic depends only on its derivatives, so it is evaluated
+  // on the data relative to the centre value c: the same quadratic form without cancellation
+  // between terms of the size of the data's square (entropy-variable data carry c_v ln T offsets)
+  const double am = a - c, bm = b - c, dp = d - c, ep = e - c;
+  double s5 = (104963.0 * (bm * bm + dp * dp) - 51001.0 * (am * bm + dp * ep) + 179098.0 * bm * dp -
+               38947.0 * (bm * ep + am * dp) + 6908.0 * (am * am + ep * ep) + 8209.0 * am * ep) *
               (1.0 / 5040.0);
   double tt = 0.5 * (fabs(s5 - s1) + fabs(s5 - s3));
   double tau = tt * tt;

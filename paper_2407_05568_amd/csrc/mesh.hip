@@ -379,6 +379,48 @@ __global__ void k_cfl(Geo G, const double *__restrict__ JU, const double *__rest
   if (flat_tid() == 0) part[flat_bid()] = ms;
 }
 
+// 2D CFL maxima with the mesh staged in LDS (mesh_tile_*): a block of 64 x 4 threads covers
+// 64 x 16 nodes, four rows per thread; the same per-node values as k_cfl<2>, so the maximum
+// (exact in any order) is the same
+#define CF_TX 64
+#define CF_TY 16
+__global__ void __launch_bounds__(256) k_cfl_t2(Geo G, const double *__restrict__ JU, const double *__restrict__ J,
+                                                const double *__restrict__ x, double *part) {
+  __shared__ MeshTile2<CF_TX, CF_TY> T;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int b0 = blockIdx.x * CF_TX, b1 = blockIdx.y * CF_TY;
+  mesh_tile_fill<CF_TX, CF_TY>(G, x, nullptr, 0.0, b0, b1, T, ty * 64 + tx, 256);
+  __syncthreads();
+  double mx = 0.0;
+#pragma unroll 1
+  for (int r = 0; r < CF_TY / 4; ++r) {
+    const int u = tx, v = ty + 4 * r;
+    const int i0 = b0 + u, i1 = b1 + v;
+    if (i0 >= G.n[0] || i1 >= G.n[1]) continue;
+    double m[2][2];
+    mesh_tile_metrics<CF_TX, CF_TY>(G, T, u, v, m);
+    mx = fmax(mx, cfl_rate_m<2>(G, JU, J, (long)i1 * G.n[0] + i0, m));
+  }
+  const double bm = block_max(mx);
+  if (flat_tid() == 0) part[flat_bid()] = bm;
+}
+
+static inline void cfl_launch(esvdw_ctx *c, const double *JU, const double *J, const double *x, double *part,
+                              long &nb, hipStream_t st) {
+  const Geo &G = c->G;
+  if (G.dim == 2) {
+    dim3 g((G.n[0] + CF_TX - 1) / CF_TX, (G.n[1] + CF_TY - 1) / CF_TY, 1);
+    nb = (long)g.x * g.y;
+    hipLaunchKernelGGL(k_cfl_t2, g, dim3(64, 4, 1), 0, st, G, JU, J, x, part);
+    return;
+  }
+  dim3 b, g;
+  node_grid(G.n[0], G.n[1], G.n[2], g, b);
+  nb = (long)g.x * g.y * g.z;
+  if (G.dim == 1) hipLaunchKernelGGL(k_cfl<1>, g, b, 0, st, G, JU, J, x, c->met, part);
+  else hipLaunchKernelGGL(k_cfl<3>, g, b, 0, st, G, JU, J, x, c->met, part);
+}
+
 // k_final (maxima) for several partial arrays at once: block q reduces part + q * stride into dst[q]
 __global__ void k_final_many(const double *__restrict__ part, long stride, long nb, double *dst) {
   const double *pq = part + blockIdx.x * stride;
@@ -591,14 +633,10 @@ int launch_limiter(esvdw_ctx *c, const double *xn, const double *xmu, double *ga
 
 int launch_cfl(esvdw_ctx *c, const double *JU, const double *J, const double *x, double *dt_dev, hipStream_t st) {
   const Geo &G = c->G;
-  dim3 b, g;
-  node_grid(G.n[0], G.n[1], G.n[2], g, b);
-  const long nb = (long)g.x * g.y * g.z;
   if (c->p.dt_fixed <= 0.0) {
     if (G.dim == 3 && launch_metrics(c, x, nullptr, c->met, nullptr, nullptr, st)) return -1;
-    if (G.dim == 1) hipLaunchKernelGGL(k_cfl<1>, g, b, 0, st, G, JU, J, x, c->met, c->part);
-    else if (G.dim == 2) hipLaunchKernelGGL(k_cfl<2>, g, b, 0, st, G, JU, J, x, c->met, c->part);
-    else hipLaunchKernelGGL(k_cfl<3>, g, b, 0, st, G, JU, J, x, c->met, c->part);
+    long nb = 0;
+    cfl_launch(c, JU, J, x, c->part, nb, st);
     hipLaunchKernelGGL(k_final_dt, dim3(1), dim3(1024), 0, st, c->part, nb, c->p.cfl, c->scal, dt_dev);
   } else {
     hipLaunchKernelGGL(k_dt, dim3(1), dim3(64), 0, st, c->p.cfl, c->p.dt_fixed, c->scal, dt_dev);
@@ -621,10 +659,9 @@ int launch_limiter_cfl(esvdw_ctx *c, const double *xn, const double *xmu, const 
   else if (G.dim == 2) hipLaunchKernelGGL(k_limiter<2>, g, b, 0, st, G, xn, xmu, c->part);
   else hipLaunchKernelGGL(k_limiter<3>, g, b, 0, st, G, xn, xmu, c->part);
   if (G.dim == 3 && launch_metrics(c, xn, nullptr, c->met, nullptr, nullptr, st)) return -1;
-  if (G.dim == 1) hipLaunchKernelGGL(k_cfl<1>, g, b, 0, st, G, JU, J, xn, c->met, pc);
-  else if (G.dim == 2) hipLaunchKernelGGL(k_cfl<2>, g, b, 0, st, G, JU, J, xn, c->met, pc);
-  else hipLaunchKernelGGL(k_cfl<3>, g, b, 0, st, G, JU, J, xn, c->met, pc);
-  hipLaunchKernelGGL(k_final_gamma_dt, dim3(1), dim3(1024), 0, st, c->part, nb, pc, nb, c->p.cfl, c->scal, dt_dev);
+  long nbc = 0;
+  cfl_launch(c, JU, J, xn, pc, nbc, st);
+  hipLaunchKernelGGL(k_final_gamma_dt, dim3(1), dim3(1024), 0, st, c->part, nb, pc, nbc, c->p.cfl, c->scal, dt_dev);
   return CHK();
 }
 

@@ -164,6 +164,36 @@ __global__ void k_nodes(Geo G, const double *__restrict__ JU, const double *__re
   node_point<D>(G, JU, J, met_in, xit_in, xn, xd, cdt, dp, dpN, nd, flags, p0, p1, p2);
 }
 
+// 2D node data with the stage mesh staged in LDS (mesh_tile_*): a block of 64 x 4 threads
+// covers 64 x 16 padded nodes, four rows per thread.
+#define ND_TX 64
+#define ND_TY 16
+__global__ void __launch_bounds__(256) k_nodes_t2(Geo G, const double *__restrict__ JU, const double *__restrict__ J,
+                                                  const double *__restrict__ xn, const double *__restrict__ xd,
+                                                  double cdt, double *__restrict__ nd, unsigned *flags) {
+  __shared__ MeshTile2<ND_TX, ND_TY> T;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int b0 = blockIdx.x * ND_TX, b1 = blockIdx.y * ND_TY;  // first padded node of the tile
+  const double *xv_src = (xd && cdt != 0.0) ? xd : nullptr;
+  mesh_tile_fill<ND_TX, ND_TY>(G, xn, xv_src, cdt, b0 - G.g[0], b1 - G.g[1], T, ty * 64 + tx, 256);
+  __syncthreads();
+#pragma unroll 1
+  for (int r = 0; r < ND_TY / 4; ++r) {
+    const int u = tx, v = ty + 4 * r;
+    const int p0 = b0 + u, p1 = b1 + v;
+    if (p0 >= G.E0 || p1 >= G.P[1]) continue;
+    const int i0 = p0 - G.g[0], i1 = p1 - G.g[1];
+    const long t = (long)p1 * G.P[0] + p0;
+    node_state<2>(G, JU, J, nd, flags, t, i0, i1, 0);
+    double m[2][2];
+    mesh_tile_metrics<ND_TX, ND_TY>(G, T, u, v, m);
+    double xv[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) xv[j] = xd ? mesh_at(G, xd, j, i0, i1, 0, 1) : 0.0;
+    node_metrics_store<2>(G, nd, t, m, xv);
+  }
+}
+
 // =============================== interface fluxes ================================
 
 template <int D, int K>
@@ -176,6 +206,54 @@ __global__ void __launch_bounds__(256, 3) k_flux(Geo G, const double *__restrict
 }
 
 // =============================== update ==========================================
+
+// 2D: the direction-0 interface fluxes of a 64 x 4 tile and the update of the 63 x 4 nodes
+// between them, in one kernel (the direction-1 fluxes are read from their buffer).  Tiles step
+// by 63 nodes along x, so the tile's last interface is also computed by the next tile; in
+// exchange the direction-0 fluxes never go through memory and the separate update kernel is
+// not needed.  The node's sums are those of update_point (direction 0, then direction 1).
+#define FU_TX 64
+#define FU_TY 4
+__global__ void __launch_bounds__(256, 3)
+    k_flux_upd2(Geo G, const double *__restrict__ nd, const double *__restrict__ F1, long nif1, int mode, int s,
+                const double *__restrict__ dtp, const double *__restrict__ base_JU, const double *__restrict__ base_J,
+                const double *__restrict__ in_JU, const double *__restrict__ in_J, double *__restrict__ out_JU,
+                double *__restrict__ out_J, unsigned *flags, const double *mx, const double *mxd, double mf,
+                double *mout) {
+  __shared__ double sP[FluxLds<2, 0, FU_TX, FU_TY, 1>::SIZE];
+  static_assert(FluxLds<2, 0, FU_TX, FU_TY, 1>::SIZE >= 5 * 256, "the interface fluxes reuse the pair-flux LDS");
+  const int bx0 = blockIdx.x * (FU_TX - 1), by0 = blockIdx.y * FU_TY;
+  double Fl[5];
+  int a0, a1, a2;
+  const bool ok = flux_tile_eval<2, 0, FU_TX, FU_TY, 1>(G, nd, flags, bx0, by0, 0, sP, Fl, a0, a1, a2);
+  __syncthreads();  // every thread has read its pair fluxes
+  const int tid = threadIdx.x, tx = tid % FU_TX, ty = tid / FU_TX;
+  if (ok) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) sP[c * 256 + tid] = Fl[c];
+  }
+  __syncthreads();
+  const int i0 = bx0 + tx, i1 = by0 + ty;
+  if (tx >= FU_TX - 1 || i0 >= G.n[0] || i1 >= G.n[1]) return;
+  const long t = (long)i1 * G.n[0] + i0;
+  double L[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) L[c] = 0.0;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) L[c] += (sP[c * 256 + tid] - sP[c * 256 + tid + 1]) * G.idxi[0];
+  {
+    const long r = (long)i1 * G.n[0] + i0;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) L[c] += (F1[(long)c * nif1 + r] - F1[(long)c * nif1 + r + G.n[0]]) * G.idxi[1];
+  }
+  update_combine<2>(G, L, t, mode, s, dtp, base_JU, base_J, in_JU, in_J, out_JU, out_J, flags);
+  if (mout) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) mout[(long)j * G.N + t] = mx[(long)j * G.N + t] + mf * (*dtp) * mxd[(long)j * G.N + t];
+  }
+}
+
+
 
 template <int D>
 __global__ void k_update(Geo G, const double *__restrict__ F0, const double *__restrict__ F1,
@@ -282,7 +360,21 @@ static int rhs_pipeline_d(esvdw_ctx *c, const double *JU, const double *J, const
   dim3 gn, bn, gu, bu;
   node_grid(G.E0, G.P[1], G.P[2], gn, bn);
   node_grid(G.n[0], G.n[1], G.n[2], gu, bu);
-  hipLaunchKernelGGL(k_nodes<D>, gn, bn, 0, st, G, JU, J, met, xit, xn, xd, cdt, c->dprod, c->dpN, c->node, c->flags);
+  if (D == 2 && !met) {
+    dim3 gt((G.E0 + ND_TX - 1) / ND_TX, (G.P[1] + ND_TY - 1) / ND_TY, 1);
+    hipLaunchKernelGGL(k_nodes_t2, gt, dim3(64, 4, 1), 0, st, G, JU, J, xn, xd, cdt, c->node, c->flags);
+  } else {
+    hipLaunchKernelGGL(k_nodes<D>, gn, bn, 0, st, G, JU, J, met, xit, xn, xd, cdt, c->dprod, c->dpN, c->node,
+                       c->flags);
+  }
+  if (D == 2) {
+    // direction 1 first; the direction-0 flux kernel then also forms the update
+    launch_flux_d<D>(c, 1, st);
+    dim3 gf((G.n[0] + FU_TX - 2) / (FU_TX - 1), (G.n[1] + FU_TY - 1) / FU_TY, 1);
+    hipLaunchKernelGGL(k_flux_upd2, gf, dim3(256), 0, st, G, c->node, c->flux[1], c->nif[1], mode, s, dtp, bJU, bJ,
+                       JU, J, oJU, oJ, c->flags, mx, mxd, mf, mout);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  }
   launch_flux_d<D>(c, 0, st);
   if (D > 1) launch_flux_d<D>(c, 1, st);
   if (D > 2) launch_flux_d<D>(c, 2, st);

@@ -28,16 +28,12 @@ __device__ __forceinline__ long ghost_metric_src(const Geo &G, int i0, int i1, i
   return lin(G, ii[0], ii[1], ii[2]);
 }
 
-// node data of padded node (p0, p1, p2) into the node buffer nd
+// thermodynamic node data (everything but the metrics) of node (i0, i1, i2) into slot t of
+// the node buffer nd
 template <int D>
-__device__ __forceinline__ void node_point(const Geo &G, const double *__restrict__ JU, const double *__restrict__ J,
-                                           const double *__restrict__ met_in, const double *__restrict__ xit_in,
-                                           const double *__restrict__ xn, const double *__restrict__ xd, double cdt,
-                                           const double *__restrict__ dp, long dpN, double *__restrict__ nd,
-                                           unsigned *flags, int p0, int p1, int p2) {
+__device__ __forceinline__ void node_state(const Geo &G, const double *__restrict__ JU, const double *__restrict__ J,
+                                           double *__restrict__ nd, unsigned *flags, long t, int i0, int i1, int i2) {
   using F = NF_<D>;
-  const long t = ((long)p2 * G.P[1] + p1) * G.P[0] + p0;
-  const int i0 = p0 - G.g[0], i1 = p1 - G.g[1], i2 = p2 - G.g[2];
   long s = state_index(G, i0, i1, i2);
   double iJ = 1.0 / J[s];
   double rho = JU[s] * iJ;
@@ -78,6 +74,37 @@ __device__ __forceinline__ void node_point(const Geo &G, const double *__restric
   // entropy variables: V = (-s + (e + p/rho - |v|^2/2)/T, v/T, -1/T), s = c_v ln T + R ln(1/rho - b)
   double sent = G.cv * lnt + G.R * (lnb - lnr);
   nd[(long)F::V1 * G.PN + t] = -sent + (e + p * irho - 0.5 * v2) * iT;
+}
+
+// metrics of slot t of the node buffer: m[k][j] = J dxi_k/dx_j, and J dxi_k/dt = -xv . m[k]
+template <int D>
+__device__ __forceinline__ void node_metrics_store(const Geo &G, double *__restrict__ nd, long t, const double (&m)[D][D],
+                                                   const double (&xv)[D]) {
+  using F = NF_<D>;
+#pragma unroll
+  for (int k = 0; k < D; ++k)
+#pragma unroll
+    for (int j = 0; j < D; ++j) nd[(long)(F::MS + k * D + j) * G.PN + t] = m[k][j];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    double s2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) s2 -= xv[j] * m[k][j];
+    nd[(long)(F::XS + k) * G.PN + t] = s2;
+  }
+}
+
+// node data of padded node (p0, p1, p2) into the node buffer nd
+template <int D>
+__device__ __forceinline__ void node_point(const Geo &G, const double *__restrict__ JU, const double *__restrict__ J,
+                                           const double *__restrict__ met_in, const double *__restrict__ xit_in,
+                                           const double *__restrict__ xn, const double *__restrict__ xd, double cdt,
+                                           const double *__restrict__ dp, long dpN, double *__restrict__ nd,
+                                           unsigned *flags, int p0, int p1, int p2) {
+  using F = NF_<D>;
+  const long t = ((long)p2 * G.P[1] + p1) * G.P[0] + p0;
+  const int i0 = p0 - G.g[0], i1 = p1 - G.g[1], i2 = p2 - G.g[2];
+  node_state<D>(G, JU, J, nd, flags, t, i0, i1, i2);
   // metrics
   if (met_in) {
     unsigned mir;
@@ -109,20 +136,10 @@ __device__ __forceinline__ void node_point(const Geo &G, const double *__restric
 #pragma unroll
         for (int j = 0; j < D; ++j) m[k][j] = metric_at<D>(G, xn, xd, cdt, dp, dpN, k, j, i0, i1, i2);
     }
-#pragma unroll
-    for (int k = 0; k < D; ++k)
-#pragma unroll
-      for (int j = 0; j < D; ++j) nd[(long)(F::MS + k * D + j) * G.PN + t] = m[k][j];
     double xv[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) xv[j] = xd ? mesh_at(G, xd, j, i0, i1, i2, 1) : 0.0;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      double s2 = 0.0;
-#pragma unroll
-      for (int j = 0; j < D; ++j) s2 -= xv[j] * m[k][j];
-      nd[(long)(F::XS + k) * G.PN + t] = s2;
-    }
+    node_metrics_store<D>(G, nd, t, m, xv);
   }
 }
 
@@ -192,7 +209,7 @@ __device__ __forceinline__ void ec_pair(const Geo &G, const Pq<D> &l, const Pq<D
   const double obl = 1.0 - G.b * l.rho, obr = 1.0 - G.b * r.rho;
   const double dR = logmean_den(l.rho, r.rho), dB = logmean_den(obl, obr), dT = logmean_den(l.T, r.T);
   const double sT = l.T + r.T;
-  const double t1 = dR * dB, t2 = dT * sT, rq = 1.0 / (t1 * t2), r1 = rq * t2, r2 = rq * t1;
+  const double t1 = dR * dB, t2 = dT * sT, rq = rcp_nr(t1 * t2), r1 = rq * t2, r2 = rq * t1;
   double iTmean = 2.0 * (r2 * dT);
   double Dd = G.R * inv_logmean_r(l.rho, r.rho, l.lr, r.lr, r1 * dB) + Rb_Pi - 2.0 * G.a * iTmean;
   if (G.b > 0.0) Dd += G.R * G.b * inv_logmean_r(obl, obr, l.lb, r.lb, r1 * dR);
@@ -203,7 +220,7 @@ __device__ __forceinline__ void ec_pair(const Geo &G, const Pq<D> &l, const Pq<D
   double Kk = 0.25 * v2T - G.cv * Tm * inv_logmean_r(l.T, r.T, l.lt, r.lt, r2 * sT) + 2.0 * G.a * rTm;
   if (!(Dd > 0.0)) bad = 1u;
   // and the two final divisions (by D and by {1/T}) share another
-  const double rd = 1.0 / (Dd * iTm);
+  const double rd = rcp_nr(Dd * iTm);
   double Fr = (rum * A + gm * um) * (rd * iTm);
   double pt = rhom * Tm * gm;
   double sum = 0.0;
@@ -285,12 +302,13 @@ template <int D, int K, int TX, int TY, int TZ> struct FluxLds {
 };
 
 // One 256-thread block computes the interface fluxes of the tile whose first interface is
-// (bx0, by0, bz0) and writes them to Fo (component-major, nif interfaces per component).
-// sP: FluxLds<...>::SIZE doubles of LDS.  Every thread reaches the internal barrier.
+// (bx0, by0, bz0): this thread's interface (a0, a1, a2) into Fl (nv + 1 values: the ES flux and
+// the GCL flux of J dxi_K/dt); false if the thread has no interface.  sP: FluxLds<...>::SIZE
+// doubles of LDS.  Every thread reaches the internal barrier.
 template <int D, int K, int TX, int TY, int TZ>
-__device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict__ nd, double *__restrict__ Fo,
-                                          long nif, unsigned *flags, int bx0, int by0, int bz0,
-                                          double *__restrict__ sP) {
+__device__ __forceinline__ bool flux_tile_eval(const Geo &G, const double *__restrict__ nd, unsigned *flags, int bx0,
+                                               int by0, int bz0, double *__restrict__ sP, double (&Fl)[D + 3],
+                                               int &a0, int &a1, int &a2) {
   using F = NF_<D>;
   static_assert(TX * TY * TZ == 256, "flux tiles map one interface to each of 256 threads");
   using TL = TileShape<TX, TY, TZ>;
@@ -343,11 +361,13 @@ __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict
 
   // ---- phase 2: this thread's interface ----
   const int tx = tid % TL::X, ty = (tid / TL::X) % TL::Y, tz = tid / (TL::X * TL::Y);
-  const int a0 = bx0 + tx, a1 = by0 + ty, a2 = bz0 + tz;  // interface index (along K: 0..n_K)
+  a0 = bx0 + tx;  // interface index (along K: 0..n_K)
+  a1 = by0 + ty;
+  a2 = bz0 + tz;
   const int e0 = G.n[0] + (K == 0), e1 = G.n[1] + (K == 1), e2 = G.n[2] + (K == 2);
   if (a0 >= e0 || a1 >= e1 || a2 >= e2) {
     if (bad) raise_flag(flags, ESVDW_F_MEANCONSTRAINT);
-    return;
+    return false;
   }
   const int i0 = a0 - (K == 0), i1 = a1 - (K == 1), i2 = a2 - (K == 2);  // left node i
   // LDS item of node i (local coordinates shifted by 2 along K)
@@ -365,9 +385,9 @@ __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict
     double rl = nd[F::RHO * G.PN + pc], rr = nd[F::RHO * G.PN + pr];
     double pl = nd[F::P * G.PN + pc], pq = nd[F::P * G.PN + pr];
     // rho/p at the two nodes and its logarithm
-    const double rpp = 1.0 / (pl * pq);
+    const double rpp = rcp_nr(pl * pq);
     double zl = rl * (pq * rpp), zr = rr * (pl * rpp);
-    const double dR = logmean_den(rl, rr), dZ = logmean_den(zl, zr), rRZ = 1.0 / (dR * dZ);
+    const double dR = logmean_den(rl, rr), dZ = logmean_den(zl, zr), rRZ = rcp_nr(dR * dZ);
     double ilr = inv_logmean_r(rl, rr, nd[F::LNR * G.PN + pc], nd[F::LNR * G.PN + pr], rRZ * dZ);
     double ilz = inv_logmean_r(zl, zr, nd[F::LNR * G.PN + pc] - nd[F::LNP * G.PN + pc],
                                nd[F::LNR * G.PN + pr] - nd[F::LNP * G.PN + pr], rRZ * dR);
@@ -383,7 +403,7 @@ __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict
     double mtb = 0.5 * (nd[(long)(F::XS + K) * G.PN + pc] + nd[(long)(F::XS + K) * G.PN + pr]);
     double L = sqrt(L2);
     // L(rho) = 1/ilr and 1/L share a division
-    const double rLL = 1.0 / (ilr * L);
+    const double rLL = rcp_nr(ilr * L);
     double rb = rLL * L;       // L(rho)
     double iL = rLL * ilr;
     double pb = rb * ilz;      // L(rho)/L(rho/p)
@@ -393,7 +413,7 @@ __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict
     // 1/(c_v ac) share a division
     double c2o = (1.0 + G.delta) * G.R * Tb - 2.0 * G.a * rb * ob * ob;
     double ac = G.R * Tb - 2.0 * G.a * rb * ob * ob;
-    const double rD = 1.0 / (ob * c2o * ac);
+    const double rD = rcp_nr(ob * c2o * ac);
     double iob = rD * (c2o * ac);
     double c2 = c2o * iob * iob;
     double ic2 = ob * ob * (rD * (ob * ac));
@@ -477,7 +497,7 @@ __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict
       double jn = np * dm - nm * dp, j0 = W[3][c] - W[2][c];
       // a plain jump below the rounding scale of W (2^-40 of its terms) counts as zero
       if (fabs(j0) <= ldexp(As[c], -40)) j0 = 0.0;
-      y[c] = ((jn > 0.0 && j0 > 0.0) || (jn < 0.0 && j0 < 0.0)) ? jn / (dp * dm) : 0.0;
+      y[c] = ((jn > 0.0 && j0 > 0.0) || (jn < 0.0 && j0 < 0.0)) ? jn * rcp_nr(dp * dm) : 0.0;
     }
     // R y in the rotated frame, then rotate the momentum back (T^T)
     double b0 = E.s0 * y[0], b1 = E.s1 * y[1], b2 = E.s0 * y[D + 1];
@@ -501,7 +521,6 @@ __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict
     }
     dd[D + 1] = dE;
   }
-  double Fl[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const double *P1 = sP + (c * 3 + 0) * Q, *P2 = sP + (c * 3 + 1) * Q, *P3 = sP + (c * 3 + 2) * Q;
@@ -509,13 +528,62 @@ __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict
     if (c < NV) Fl[c] -= h * dd[c];
   }
   if (bad) raise_flag(flags, ESVDW_F_MEANCONSTRAINT);
+  return true;
+}
+
+// flux_tile_eval, the fluxes written to Fo (component-major, nif interfaces per component)
+template <int D, int K, int TX, int TY, int TZ>
+__device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict__ nd, double *__restrict__ Fo,
+                                          long nif, unsigned *flags, int bx0, int by0, int bz0,
+                                          double *__restrict__ sP) {
+  double Fl[D + 3];
+  int a0, a1, a2;
+  if (!flux_tile_eval<D, K, TX, TY, TZ>(G, nd, flags, bx0, by0, bz0, sP, Fl, a0, a1, a2)) return;
+  const int e0 = G.n[0] + (K == 0), e1 = G.n[1] + (K == 1);
   const long ti = ((long)a2 * e1 + a1) * e0 + a0;
 #pragma unroll
-  for (int c = 0; c < NC; ++c) Fo[(long)c * nif + ti] = Fl[c];
+  for (int c = 0; c < D + 3; ++c) Fo[(long)c * nif + ti] = Fl[c];
 }
 
 
 // =============================== update ==========================================
+
+// RK-stage output at node slot t from the semi-discrete RHS L (nv + 1 values).  mode 0: write
+// dJU, dJ.  mode 1: SSP-RK3 stage s combination with dt from the device.
+template <int D>
+__device__ __forceinline__ void update_combine(const Geo &G, const double (&L)[D + 3], long t, int mode, int s,
+                                               const double *__restrict__ dtp, const double *__restrict__ base_JU,
+                                               const double *__restrict__ base_J, const double *__restrict__ in_JU,
+                                               const double *__restrict__ in_J, double *__restrict__ out_JU,
+                                               double *__restrict__ out_J, unsigned *flags) {
+  constexpr int NV = D + 2;
+  bool nan = false;
+  if (mode == 0) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      out_JU[(long)c * G.N + t] = L[c];
+      nan |= isnan(L[c]);
+    }
+    out_J[t] = L[NV];
+    nan |= isnan(L[NV]);
+  } else {
+    double dt = *dtp;
+#pragma unroll
+    for (int c = 0; c <= NV; ++c) {
+      const double *inp = c < NV ? in_JU + (long)c * G.N : in_J;
+      const double *bp = c < NV ? base_JU + (long)c * G.N : base_J;
+      double y = inp[t] + dt * L[c];
+      double o;
+      if (s == 0) o = y;
+      else if (s == 1) o = 0.75 * bp[t] + 0.25 * y;
+      else o = (1.0 / 3.0) * bp[t] + (2.0 / 3.0) * y;
+      nan |= isnan(o);
+      if (c < NV) out_JU[(long)c * G.N + t] = o;
+      else out_J[t] = o;
+    }
+  }
+  if (nan) raise_flag(flags, ESVDW_F_NAN);
+}
 
 // mode 0: write dJU, dJ.  mode 1: SSP-RK3 stage s combination with dt from the device.
 template <int D>
@@ -547,32 +615,7 @@ __device__ __forceinline__ void update_point(const Geo &G, const double *__restr
 #pragma unroll
     for (int c = 0; c <= NV; ++c) L[c] += (F2[(long)c * nif2 + r] - F2[(long)c * nif2 + r + st]) * G.idxi[2];
   }
-  bool nan = false;
-  if (mode == 0) {
-#pragma unroll
-    for (int c = 0; c < NV; ++c) {
-      out_JU[(long)c * G.N + t] = L[c];
-      nan |= isnan(L[c]);
-    }
-    out_J[t] = L[NV];
-    nan |= isnan(L[NV]);
-  } else {
-    double dt = *dtp;
-#pragma unroll
-    for (int c = 0; c <= NV; ++c) {
-      const double *inp = c < NV ? in_JU + (long)c * G.N : in_J;
-      const double *bp = c < NV ? base_JU + (long)c * G.N : base_J;
-      double y = inp[t] + dt * L[c];
-      double o;
-      if (s == 0) o = y;
-      else if (s == 1) o = 0.75 * bp[t] + 0.25 * y;
-      else o = (1.0 / 3.0) * bp[t] + (2.0 / 3.0) * y;
-      nan |= isnan(o);
-      if (c < NV) out_JU[(long)c * G.N + t] = o;
-      else out_J[t] = o;
-    }
-  }
-  if (nan) raise_flag(flags, ESVDW_F_NAN);
+  update_combine<D>(G, L, t, mode, s, dtp, base_JU, base_J, in_JU, in_J, out_JU, out_J, flags);
 }
 
 
@@ -580,11 +623,10 @@ __device__ __forceinline__ void update_point(const Geo &G, const double *__restr
 
 // CFL spectral-radius sum at node (i0, i1, i2): sum_k (|v . m_k| + |m_k| c) / (J dxi_k) with
 // m_k = J grad xi_k; metrics of the mesh x computed in place (1D/2D) or read from met (3D)
+// the same sum with the metrics mm[k][j] of the node given
 template <int D>
-__device__ __forceinline__ double cfl_rate(const Geo &G, const double *__restrict__ JU, const double *__restrict__ J,
-                                           const double *__restrict__ x, const double *__restrict__ met, int i0,
-                                           int i1, int i2) {
-  const long t = lin(G, i0, i1, i2);
+__device__ __forceinline__ double cfl_rate_m(const Geo &G, const double *__restrict__ JU, const double *__restrict__ J,
+                                             long t, const double (&mm)[D][D]) {
   double s = 0.0;
   double iJ = 1.0 / J[t];
   double rho = JU[t] * iJ, v[D], v2 = 0.0;
@@ -595,16 +637,6 @@ __device__ __forceinline__ double cfl_rate(const Geo &G, const double *__restric
   }
   double T = eos_T_rho_e(G, rho, JU[(long)(D + 1) * G.N + t] * iJ / rho - 0.5 * v2);
   double c = sqrt(eos_c2(G, rho, T));
-  double mm[D][D];
-  if constexpr (D == 2) {
-    metrics2(G, x, nullptr, 0.0, i0, i1, mm);
-  } else {
-#pragma unroll
-    for (int k = 0; k < D; ++k)
-#pragma unroll
-      for (int j = 0; j < D; ++j)
-        mm[k][j] = D == 3 ? met[(long)(k * D + j) * G.N + t] : metric_at<D>(G, x, nullptr, 0.0, nullptr, 0, k, j, i0, i1, i2);
-  }
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     double L2 = 0.0, vn = 0.0;
@@ -617,4 +649,22 @@ __device__ __forceinline__ double cfl_rate(const Geo &G, const double *__restric
     s += (fabs(vn) + sqrt(L2) * c) * iJ * G.idxi[k];
   }
   return s;
+}
+
+template <int D>
+__device__ __forceinline__ double cfl_rate(const Geo &G, const double *__restrict__ JU, const double *__restrict__ J,
+                                           const double *__restrict__ x, const double *__restrict__ met, int i0,
+                                           int i1, int i2) {
+  const long t = lin(G, i0, i1, i2);
+  double mm[D][D];
+  if constexpr (D == 2) {
+    metrics2(G, x, nullptr, 0.0, i0, i1, mm);
+  } else {
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+        mm[k][j] = D == 3 ? met[(long)(k * D + j) * G.N + t] : metric_at<D>(G, x, nullptr, 0.0, nullptr, 0, k, j, i0, i1, i2);
+  }
+  return cfl_rate_m<D>(G, JU, J, t, mm);
 }

@@ -1,17 +1,17 @@
 """GPU parity: the HIP library (through its C ABI) against the oracle on the same seeded
-inputs.  Floating-point bar, per output field: max |gpu - oracle| <= tol * max |oracle|.
-
-tol = 1e-12 for one call (metrics, RHS, stage, mesh pieces) and 1e-9 on U after 100 full
-steps, raised only where the scheme itself is less well conditioned than that: the
-nonlinear MR-WENO weights amplify rounding of W (whose c_v ln T terms are large for
-delta = 0.0125), so each test first measures the oracle's own sensitivity kappa (the
-relative output change when every input is perturbed by one unit in the last place) and
-uses tol = max(1e-12, 8 kappa) (per call) or max(1e-9, 8 kappa) (100 steps)."""
+inputs.  Floating-point bar, per output field and node: |gpu - oracle| / max |oracle| <= 1e-12
+for one call (metrics, RHS, stage, mesh pieces) and <= 1e-9 on U after 100 full steps, except
+at nodes where the oracle itself moves by more than 1/8 of that under one-ulp perturbations of
+its input (the nonlinear MR-WENO weights and the dissipation's sign test amplify rounding
+there); such a node is held to 8 times its own sensitivity instead, and the share of these
+nodes is reported (tests/parity.py)."""
 
 import numpy as np
 import pytest
 
 from paper_2407_05568_amd import synth
+
+import parity
 
 pytestmark = pytest.mark.gpu
 
@@ -46,21 +46,7 @@ def relerr(g, r):
     return max(out)
 
 
-ULP = 2.0 ** -52
-
-
-def _perturb(a, seed):
-    rng = np.random.default_rng(seed)
-    return a * (1.0 + ULP * rng.choice([-1.0, 1.0], size=a.shape))
-
-
-def rhs_sensitivity(o, JU, J, met, xit, ref):
-    """kappa: the oracle's relative RHS change for a 1-ulp relative perturbation of the state."""
-    k = 0.0
-    for seed in (1, 2):
-        d = o.rhs(_perturb(JU, seed), J, met, xit)[0]
-        k = max(k, relerr(d, ref))
-    return k
+SEEDS = (1, 2, 3, 4)
 
 
 def _setup(torch, p, seed, kind):
@@ -121,11 +107,9 @@ def test_metrics_and_rhs_parity(orc, torch_dev, dim, bc, kind, diss):
     dJU_g = torch.empty_like(JU_g)
     dJ_g = torch.empty_like(J_g)
     ctx.es_rhs(JU_g, J_g, T(torch, met_r), T(torch, xit_r), dJU_g, dJ_g)
-    e = relerr(N(dJU_g), dJU_r)
-    kappa = rhs_sensitivity(o, JU_r, J_r, met_r, xit_r, dJU_r)
-    tol = max(TOL_CALL, 8 * kappa)
-    print("rhs rel err %.3e kappa %.3e tol %.3e" % (e, kappa, tol), dim, bc, kind, diss)
-    assert e < tol
+    pert = [o.rhs(parity.perturb(JU_r, sd), J_r, met_r, xit_r)[0] for sd in SEEDS]
+    parity.check("rhs %dD %s %s diss=%d %s" % (dim, bc, kind, diss, "x".join(map(str, SIZES[dim]))), N(dJU_g),
+                 dJU_r, pert, TOL_CALL)
     assert relerr(N(dJ_g)[None], dJ_r[None]) < TOL_CALL
     assert ctx.status() == 0 and o.flags() == 0
 
@@ -154,15 +138,13 @@ def test_3d_multitile_metrics_and_stages(orc, torch_dev, bc):
     dtg = T(torch, np.array([dt]))
     JUs, Js = JU, J
     for s in range(3):
-        kappa = relerr(o.rk_stage(s, dt, JU, J, _perturb(JUs, 7), Js, x, xd)[0], o.rk_stage(s, dt, JU, J, JUs, Js, x, xd)[0])
+        pert = [o.rk_stage(s, dt, JU, J, parity.perturb(JUs, sd), Js, x, xd)[0] for sd in SEEDS]
         JUo_r, Jo_r = o.rk_stage(s, dt, JU, J, JUs, Js, x, xd)
         JUo = torch.empty((5,) + o.shape, dtype=torch.float64, device="cuda")
         Jo = torch.empty(o.shape, dtype=torch.float64, device="cuda")
         ctx.rk_stage(s, dtg, T(torch, JU), T(torch, J), T(torch, JUs), T(torch, Js), T(torch, x), T(torch, xd), JUo, Jo,
                      None)
-        e, tol = relerr(N(JUo), JUo_r), max(TOL_CALL, 8 * kappa)
-        print("3D 40x22x30 %s stage %d rel err %.3e tol %.3e" % (bc, s, e, tol))
-        assert e < tol
+        parity.check("stage %d 3D %s smooth 40x22x30" % (s, bc), N(JUo), JUo_r, pert, TOL_CALL)
         assert relerr(N(Jo)[None], Jo_r[None]) < TOL_CALL
         JUs, Js = JUo_r, Jo_r
     assert ctx.status() == 0 and o.flags() == 0
@@ -184,24 +166,16 @@ def test_rk_stage_parity(orc, torch_dev, dim, bc, kind, diss):
     JUs = JU * (1 + 1e-3 * rng.standard_normal(JU.shape))
     Js = J * (1 + 1e-4 * rng.standard_normal(J.shape))
     dtg = T(torch, np.array([dt]))
-    # conditioning of the stage: oracle against itself with a 1-ulp perturbed stage input
-    kappa = 0.0
-    for s in range(3):
-        a = o.rk_stage(s, dt, JU, J, JUs, Js, x, xd)[0]
-        b = o.rk_stage(s, dt, JU, J, _perturb(JUs, 3), Js, x, xd)[0]
-        kappa = max(kappa, relerr(b, a))
-    tol = max(TOL_CALL, 8 * kappa)
     for s in range(3):
         JUo_r, Jo_r = o.rk_stage(s, dt, JU, J, JUs, Js, x, xd)
+        pert = [o.rk_stage(s, dt, JU, J, parity.perturb(JUs, sd), Js, x, xd)[0] for sd in SEEDS]
         JUo = torch.empty((dim + 2,) + o.shape, dtype=torch.float64, device="cuda")
         Jo = torch.empty(o.shape, dtype=torch.float64, device="cuda")
         xn_g = T(torch, x)
         xnext = torch.empty_like(xn_g)
         ctx.rk_stage(s, dtg, T(torch, JU), T(torch, J), T(torch, JUs), T(torch, Js), xn_g, T(torch, xd), JUo, Jo,
                      xnext if s == 2 else None)
-        e = relerr(N(JUo), JUo_r)
-        print("stage %d rel err %.3e tol %.3e" % (s, e, tol))
-        assert e < tol
+        parity.check("stage %d %dD %s %s diss=%d" % (s, dim, bc, kind, diss), N(JUo), JUo_r, pert, TOL_CALL)
         assert relerr(N(Jo)[None], Jo_r[None]) < TOL_CALL
         if s == 2:
             assert np.abs(N(xnext) - (x + dt * xd)).max() < 1e-15
@@ -275,19 +249,15 @@ def test_hundred_steps(orc, torch_dev, dim, bc, kind, n):
     JUg = torch.empty((dim + 2,) + o.shape, dtype=torch.float64, device="cuda")
     ctx.init_state(T(torch, prim), Jg, JUg)
     dtg = torch.zeros(1, dtype=torch.float64, device="cuda")
-    JUp, Jp, xp = _perturb(JU, 7), J.copy(), x.copy()
+    runs = [(JU, J, x)] + [(parity.perturb(JU, sd), J.copy(), x.copy()) for sd in SEEDS]
     for _ in range(100):
-        JU, J, x, dt = o.step(JU, J, x, moving=True)
-        JUp, Jp, xp, _ = o.step(JUp, Jp, xp, moving=True)
+        runs = [o.step(a, b, c, moving=True)[:3] for a, b, c in runs]
         ctx.step(JUg, Jg, xg, 1, dtg)
     torch.cuda.synchronize()
-    kappa = max(relerr(JUp / Jp[None], JU / J[None]), np.abs(xp - x).max())
-    tol = max(TOL_RUN, 8 * kappa)
-    eu = relerr(N(JUg) / N(Jg)[None], JU / J[None])
-    ex = np.abs(N(xg) - x).max()
-    print("100 steps", dim, kind, "U rel err %.3e x err %.3e kappa %.3e tol %.3e" % (eu, ex, kappa, tol))
-    assert eu < tol
-    assert ex < tol
+    (JU, J, x), pert = runs[0], runs[1:]
+    name = "100 steps %dD %s %s" % (dim, kind, "x".join(map(str, n)))
+    parity.check(name + " U", N(JUg) / N(Jg)[None], JU / J[None], [a / b[None] for a, b, _ in pert], TOL_RUN)
+    parity.check(name + " x", N(xg), x, [c for _, _, c in pert], TOL_RUN)
     assert ctx.status() == 0 and o.flags() == 0
 
 

@@ -3,18 +3,21 @@ oracle: the adaptation of the initial mesh (redistribution passes on the initial
 RK stage on the adapted mesh, several full steps, and the invariants of a run to the final
 time.
 
-Bars: the mesh passes and the single stage are compared at max(1e-12, 8 kappa); the multi-step
-run at max(1e-9, 8 kappa), with kappa the oracle's own change under a 1-ulp perturbation of its
-input.  On this data kappa is large after one step (~1e-5 relative): next to the sphere the
-sign test of the dissipation meets real jumps that are tiny, and which side of zero they fall on
-decides whether a full reconstructed jump is dissipated, so rounding-level differences become
-O(1e-5) within a step, in the oracle as much as between oracle and GPU."""
+Bars (tests/parity.py): the mesh passes and the single stage are compared at 1e-12 per field and
+node, the multi-step run at 1e-9, except at nodes where the oracle's own change under 1-ulp
+perturbations of its input is larger than 1/8 of that, which are held to 8 times that change.
+On this data that change is large after one step (~1e-5 relative) at some nodes: next to the
+sphere the sign test of the dissipation meets real jumps that are tiny, and which side of zero
+they fall on decides whether a full reconstructed jump is dissipated, so rounding-level
+differences become O(1e-5) within a step, in the oracle as much as between oracle and GPU."""
 import os
 
 import numpy as np
 import pytest
 
 from paper_2407_05568_amd import shock3d, synth
+
+import parity
 
 pytestmark = pytest.mark.gpu
 
@@ -28,17 +31,6 @@ def torch_dev():
     from paper_2407_05568_amd import esvdw
     esvdw.lib()
     return torch
-
-
-def relerr(g, r):
-    g = np.asarray(g).reshape(np.shape(g)[0], -1)
-    r = np.asarray(r).reshape(g.shape)
-    return max(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300) for a, b in zip(g, r))
-
-
-def ulp_perturb(a, seed):
-    rng = np.random.default_rng(seed)
-    return a * (1.0 + 2.0 ** -52 * rng.choice([-1.0, 1.0], size=a.shape))
 
 
 def oracle_preadapt(o, p, x, passes):
@@ -57,29 +49,27 @@ def adapted(orc):
     o = orc.Oracle(p)
     x0 = o.uniform_mesh()
     x, J, JU = oracle_preadapt(o, p, x0, PASSES)
-    xp, _, _ = oracle_preadapt(o, p, ulp_perturb(x0, 3), PASSES)
+    pert = [oracle_preadapt(o, p, parity.perturb(x0, sd), PASSES) for sd in (1, 2, 3)]
     assert o.flags() == 0
-    return p, o, x0, x, J, JU, np.abs(xp - x).max()
+    return p, o, x0, x, J, JU, pert
 
 
 def test_spherical_shock_initial_mesh_matches_oracle(torch_dev, adapted):
     torch = torch_dev
     from paper_2407_05568_amd.esvdw import Context
-    p, o, x0, x, J, JU, kappa = adapted
+    p, o, x0, x, J, JU, pert = adapted
     ctx = Context(p)
     xg = torch.from_numpy(x0.copy()).cuda()
     Jg = torch.empty(o.shape, dtype=torch.float64, device="cuda")
     JUg = torch.empty((5,) + o.shape, dtype=torch.float64, device="cuda")
     done, move = shock3d.preadapt(torch, ctx, p, xg, Jg, JUg, PASSES, tol=0.0)
     torch.cuda.synchronize()
-    tol = max(1e-12, 8 * kappa)
-    ex = np.abs(xg.cpu().numpy() - x).max()
-    eJ = np.abs(Jg.cpu().numpy() - J).max()
-    eU = relerr(JUg.cpu().numpy(), JU)
-    print("initial mesh %d^3, %d passes (last move %.3f cells): x err %.2e J err %.2e JU rel err %.2e tol %.2e" % (
-        N, done, move, ex, eJ, eU, tol))
+    print("initial mesh %d^3, %d passes (last move %.3f cells)" % (N, done, move))
     assert done == PASSES
-    assert ex < tol and eJ < tol and eU < tol
+    name = "spherical shock %d^3 initial mesh, %d passes" % (N, PASSES)
+    parity.check(name + " x", xg.cpu().numpy(), x, [q[0] for q in pert], 1e-12)
+    parity.check(name + " J", Jg.cpu().numpy()[None], J[None], [q[1][None] for q in pert], 1e-12)
+    parity.check(name + " JU", JUg.cpu().numpy(), JU, [q[2] for q in pert], 1e-12)
     assert ctx.status() == 0
 
 
@@ -90,10 +80,13 @@ def test_spherical_shock_first_stage_matches_oracle(torch_dev, adapted):
     p, o, x0, x, J, JU, _ = adapted
     r = o.redistribute(JU, J, x)
     JU1, J1 = o.rk_stage(0, r["dt"], JU, J, JU, J, x, r["xdot"])
-    JUq = ulp_perturb(JU, 5)
-    rq = o.redistribute(JUq, J, x)
-    JU1q, J1q = o.rk_stage(0, rq["dt"], JUq, J, JUq, J, x, rq["xdot"])
-    kappa = max(relerr(JU1q / J1q[None], JU1 / J1[None]), relerr(rq["xdot"], r["xdot"]))
+    pu, pv = [], []
+    for sd in (1, 2, 3):
+        JUq = parity.perturb(JU, sd)
+        rq = o.redistribute(JUq, J, x)
+        JU1q, J1q = o.rk_stage(0, rq["dt"], JUq, J, JUq, J, x, rq["xdot"])
+        pu.append(JU1q / J1q[None])
+        pv.append(rq["xdot"])
     ctx = Context(p)
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     xg, Jg, JUg = T(x), T(J), T(JU)
@@ -103,12 +96,12 @@ def test_spherical_shock_first_stage_matches_oracle(torch_dev, adapted):
     JU1g, J1g = torch.empty_like(JUg), torch.empty_like(Jg)
     ctx.rk_stage(0, dt, JUg, Jg, JUg, Jg, xg, xdot, JU1g, J1g)
     torch.cuda.synchronize()
-    tol = max(1e-12, 8 * kappa)
     ed = abs(float(dt.item()) - r["dt"]) / r["dt"]
-    ev = relerr(xdot.cpu().numpy(), r["xdot"])
-    eu = relerr((JU1g / J1g[None]).cpu().numpy(), JU1 / J1[None])
-    print("first stage %d^3: dt err %.2e xdot err %.2e U err %.2e kappa %.2e tol %.2e" % (N, ed, ev, eu, kappa, tol))
-    assert ed < tol and ev < tol and eu < tol
+    print("first stage %d^3: dt err %.2e" % (N, ed))
+    assert ed < 1e-12
+    name = "spherical shock %d^3 redistribution + stage 0" % N
+    parity.check(name + " xdot", xdot.cpu().numpy(), r["xdot"], pv, 1e-12)
+    parity.check(name + " U", (JU1g / J1g[None]).cpu().numpy(), JU1 / J1[None], pu, 1e-12)
     assert ctx.status() == 0 and o.flags() == 0
 
 
@@ -121,18 +114,21 @@ def test_spherical_shock_steps_match_oracle(torch_dev, adapted):
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     xg, Jg, JUg = T(x), T(J), T(JU)
     dtg = torch.zeros(1, dtype=torch.float64, device="cuda")
-    JUp, Jp, xp = ulp_perturb(JU, 7), J.copy(), x.copy()
+    runs = [(JU, J, x)] + [(parity.perturb(JU, sd), J.copy(), x.copy()) for sd in (1, 2, 3)]
     for _ in range(steps):
-        JU, J, x, _ = o.step(JU, J, x, moving=True)
-        JUp, Jp, xp, _ = o.step(JUp, Jp, xp, moving=True)
+        runs = [o.step(a, b, c, moving=True)[:3] for a, b, c in runs]
         ctx.step(JUg, Jg, xg, 1, dtg)
     torch.cuda.synchronize()
-    kappa = max(relerr(JUp / Jp[None], JU / J[None]), np.abs(xp - x).max())
-    tol = max(1e-9, 8 * kappa)
-    eu = relerr((JUg / Jg[None]).cpu().numpy(), JU / J[None])
-    ex = np.abs(xg.cpu().numpy() - x).max()
-    print("spherical shock %d^3, %d steps: U rel err %.3e x err %.3e kappa %.3e tol %.3e" % (N, steps, eu, ex, kappa, tol))
-    assert eu < tol and ex < tol
+    (JU, J, x), pert = runs[0], runs[1:]
+    # Within these six steps a rounding-level difference anywhere near the sphere can switch the
+    # dissipation of a tiny real jump (see above), and the effect of a switch spreads over the
+    # stencil reach of 18 stages, i.e. the whole 16^3 grid: which nodes a run perturbs depends
+    # on where its rounding falls, so each field's nodes are held to that field's largest
+    # sensitivity (the single stage above is held node by node).
+    name = "spherical shock %d^3, %d steps" % (N, steps)
+    parity.check(name + " U", (JUg / Jg[None]).cpu().numpy(), JU / J[None], [a / b[None] for a, b, _ in pert], 1e-9,
+                 per_field=True)
+    parity.check(name + " x", xg.cpu().numpy(), x, [c for _, _, c in pert], 1e-9, per_field=True)
     assert ctx.status() == 0 and o.flags() == 0
 
 
