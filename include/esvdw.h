@@ -37,6 +37,7 @@ extern "C" {
 #define ESVDW_EINVAL (-1)
 #define ESVDW_EHIP (-2)
 #define ESVDW_ENOTIMPL (-3)
+#define ESVDW_ESCRATCH (-4) /* the problem exceeds a no-allocation entry point's static scratch */
 
 #define ESVDW_F_INADMISSIBLE 1u   /* a node state violates eq. coefflimit / eq. Tlimit */
 #define ESVDW_F_MEANCONSTRAINT 2u /* D <= 0 (Theorem 3.1) or a non-positive S^2 entry */
@@ -165,6 +166,20 @@ int mesh_limiter(esvdw_ctx *ctx, const double *x_n, const double *x_mu, double *
 int mesh_converged(esvdw_ctx *ctx, double *xmu_out, hipStream_t stream);
 int cfl_dt(esvdw_ctx *ctx, const double *JU, const double *J, const double *x, double *dt_dev,
            hipStream_t stream);
+
+/* cfl_dt for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): needs no context and calls no allocating
+ * routine.  The same kernels and reduction order as cfl_dt with a context made from *p, so the
+ * two give bit-identical dt.  Its per-block maxima live in a static device array of 65544 doubles
+ * (512 KiB) that each GPU the library runs on holds until the process ends; it is looked up on
+ * the first call on a device.  Limits: dim 1 or 2 (3D needs the metric scratch of a context), at
+ * most 65536 blocks (1D: ceil(n0/256); 2D: tiles of 64 x 16 nodes, ceil(n0/64) ceil(n1/16), e.g.
+ * 16384^2);
+ * ESVDW_ESCRATCH beyond that, ESVDW_EINVAL for bad parameters or pointers.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (concurrent streams or threads) race
+ * and must be serialised by the caller.  *dt_dev: the time step (device pointer). */
+int cfl_dt_noalloc(const esvdw_params *p, const double *JU, const double *J, const double *x, double *dt_dev,
+                   hipStream_t stream);
 
 /* One complete time step in place: redistribute_mesh (fixed mu) when moving != 0, else the
  * CFL time step on the fixed mesh; three rk_stage calls using the context's stage buffers;

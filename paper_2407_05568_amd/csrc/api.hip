@@ -78,6 +78,7 @@ const char *esvdw_strerror(int code) {
     case ESVDW_EINVAL: return "invalid argument";
     case ESVDW_EHIP: return "HIP error";
     case ESVDW_ENOTIMPL: return "not implemented";
+    case ESVDW_ESCRATCH: return "problem too large for the static scratch of a no-allocation entry point";
     default: return "unknown error";
   }
 }
@@ -220,6 +221,14 @@ int mesh_limiter(esvdw_ctx *c, const double *x_n, const double *x_mu, double *ga
 int cfl_dt(esvdw_ctx *c, const double *JU, const double *J, const double *x, double *dt_dev, hipStream_t st) {
   if (!c || !JU || !J || !x) return ESVDW_EINVAL;
   return launch_cfl(c, JU, J, x, dt_dev, st) ? ESVDW_EHIP : ESVDW_OK;
+}
+
+int cfl_dt_noalloc(const esvdw_params *p, const double *JU, const double *J, const double *x, double *dt_dev,
+                   hipStream_t st) {
+  if (!params_valid(p) || p->dim > 2 || !JU || !J || !x || !dt_dev) return ESVDW_EINVAL;
+  Geo G;
+  make_geo(p, &G);
+  return launch_cfl_noalloc(G, p->cfl, p->dt_fixed, JU, J, x, dt_dev, st);
 }
 
 int redistribute_mesh(esvdw_ctx *c, const double *JU, const double *J, const double *x_n, const double *warm_dx,

@@ -36,6 +36,9 @@ int launch_limiter(esvdw_ctx *c, const double *xn, const double *xmu, double *ga
 int launch_limiter_cfl(esvdw_ctx *c, const double *xn, const double *xmu, const double *JU, const double *J,
                        double *dt_dev, hipStream_t st);
 int launch_cfl(esvdw_ctx *c, const double *JU, const double *J, const double *x, double *dt_dev, hipStream_t st);
+// launch_cfl on the library's static per-device scratch (1D/2D); returns an ESVDW_* code
+int launch_cfl_noalloc(const Geo &G, double cfl, double dt_fixed, const double *JU, const double *J,
+                       const double *x, double *dt_dev, hipStream_t st);
 int launch_xdot(esvdw_ctx *c, const double *xn, const double *xmu, const double *gam, const double *dtp, double *xdot,
                 hipStream_t st);
 int launch_copy(const double *src, double *dst, long n, hipStream_t st);

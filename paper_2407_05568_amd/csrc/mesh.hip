@@ -2,6 +2,8 @@
 // of the discretised Winslow equations, movement limiter, CFL time step (eq. cfl) and the
 // mesh velocity.  Global reductions: per-block partials (wavefront shuffles, then LDS), reduced
 // by a one-block kernel into a device scalar of the context.
+#include <mutex>
+
 #include "common.h"
 #include "kernels.h"
 #include "meshdev.h"
@@ -642,6 +644,58 @@ int launch_cfl(esvdw_ctx *c, const double *JU, const double *J, const double *x,
     hipLaunchKernelGGL(k_dt, dim3(1), dim3(64), 0, st, c->p.cfl, c->p.dt_fixed, c->scal, dt_dev);
   }
   return CHK();
+}
+
+// ---- CFL time step without allocation (cfl_dt_noalloc) ------------------------------------
+// The per-block maxima and the two result slots live in a file-scope device array: each GPU
+// holds its own copy for the life of the process.  Its address differs per device and the
+// array's name is not a device address in host code, so it is looked up once per device with
+// hipGetSymbolAddress and only that pointer is passed to kernels.
+#define NOALLOC_PARTS 65536                     // per-block partial maxima (256 nodes in 1D, 1024 in 2D)
+#define NOALLOC_DOUBLES (NOALLOC_PARTS + SC_N)  // + the scalar slots k_final_dt writes
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+#define NOALLOC_MAXDEV 64
+static double *g_scratch_ptr[NOALLOC_MAXDEV];
+static std::mutex g_scratch_mu;
+
+static double *noalloc_scratch(int dev) {
+  if (dev < 0 || dev >= NOALLOC_MAXDEV) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch_ptr[dev] = (double *)ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+int launch_cfl_noalloc(const Geo &G, double cfl, double dt_fixed, const double *JU, const double *J,
+                       const double *x, double *dt_dev, hipStream_t st) {
+  // the kernels of launch_cfl: 1D one node per thread, 2D the LDS-tiled kernel
+  dim3 b, g;
+  if (G.dim == 2) {
+    g = dim3((G.n[0] + CF_TX - 1) / CF_TX, (G.n[1] + CF_TY - 1) / CF_TY, 1);
+    b = dim3(64, 4, 1);
+  } else {
+    node_grid(G.n[0], G.n[1], G.n[2], g, b);
+  }
+  const long nb = (long)g.x * g.y * g.z;
+  if (nb > NOALLOC_PARTS) return ESVDW_ESCRATCH;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return ESVDW_EHIP;
+  double *ptr = noalloc_scratch(dev);  // set-up on this device's first call
+  if (!ptr) return ESVDW_EHIP;
+  double *scal = ptr + NOALLOC_PARTS;
+  if (dt_fixed > 0.0) {
+    hipLaunchKernelGGL(k_dt, dim3(1), dim3(64), 0, st, cfl, dt_fixed, scal, dt_dev);
+  } else {
+    // every block writes its partial, so nothing needs clearing between calls
+    if (G.dim == 1) hipLaunchKernelGGL(k_cfl<1>, g, b, 0, st, G, JU, J, x, nullptr, ptr);
+    else hipLaunchKernelGGL(k_cfl_t2, g, b, 0, st, G, JU, J, x, ptr);
+    hipLaunchKernelGGL(k_final_dt, dim3(1), dim3(1024), 0, st, ptr, nb, cfl, scal, dt_dev);
+  }
+  return CHK() ? ESVDW_EHIP : ESVDW_OK;
 }
 
 int launch_limiter_cfl(esvdw_ctx *c, const double *xn, const double *xmu, const double *JU, const double *J,

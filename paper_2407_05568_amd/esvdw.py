@@ -10,7 +10,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("ESVDW_LIB") or os.path.join(HERE, "libesvdw.so")
 
-OK, EINVAL, EHIP, ENOTIMPL = 0, -1, -2, -3
+OK, EINVAL, EHIP, ENOTIMPL, ESCRATCH = 0, -1, -2, -3, -4
 F_INADMISSIBLE, F_MEANCONSTRAINT, F_NAN, F_NOTCONVERGED = 1, 2, 4, 8
 BC = {"periodic": 0, "outflow": 1}
 MONITOR = {"vdw": 0, "sine": 1}
@@ -19,7 +19,7 @@ MONVAR = {"rho": 0, "G": 1}
 # entry points declared in include/esvdw.h
 SYMBOLS = ["esvdw_create", "esvdw_destroy", "esvdw_get_status", "esvdw_strerror", "init_mesh", "init_state",
            "compute_metrics", "es_rhs", "rk_stage", "redistribute_mesh", "mesh_monitor", "mesh_jacobi", "mesh_sor",
-           "mesh_limiter", "mesh_converged", "cfl_dt", "esvdw_step", "esvdw_bench_kernel", "mlp_features", "mlp_infer",
+           "mesh_limiter", "mesh_converged", "cfl_dt", "cfl_dt_noalloc", "esvdw_step", "esvdw_bench_kernel", "mlp_features", "mlp_infer",
            "mlp_grad", "mlp_adam", "esvdw_batch_create", "esvdw_batch_destroy", "esvdw_batch_offsets",
            "esvdw_batch_init_mesh", "esvdw_batch_init_state", "esvdw_batch_stage", "esvdw_batch_redistribute",
            "esvdw_batch_step",
@@ -100,6 +100,7 @@ def lib():
             "mesh_limiter": (I, [_VP] * 5),
             "mesh_converged": (I, [_VP] * 3),
             "cfl_dt": (I, [_VP] * 6),
+            "cfl_dt_noalloc": (I, [ctypes.POINTER(Params)] + [_VP] * 5),
             "esvdw_step": (I, [_VP, _VP, _VP, _VP, I, _VP, _VP]),
             "esvdw_bench_kernel": (I, [_VP, I, I, _VP]),
             "mlp_features": (I, [_VP] * 5),
@@ -149,6 +150,14 @@ class LibError(RuntimeError):
 def _check(rc, what):
     if rc != OK:
         raise LibError("%s failed: %s (%d)" % (what, lib().esvdw_strerror(rc).decode(), rc))
+
+
+def cfl_dt_noalloc(p, JU, J, x, dt_dev, stream=None):
+    """cfl_dt without a context: the library's static per-device scratch, no allocation
+    (1D/2D; LibError with ESCRATCH when the grid exceeds that scratch)."""
+    params = params_from(p)
+    _check(lib().cfl_dt_noalloc(ctypes.byref(params), _ptr(JU), _ptr(J), _ptr(x), _ptr(dt_dev), _stream(stream)),
+           "cfl_dt_noalloc")
 
 
 class Context:
