@@ -67,7 +67,7 @@ def profile_record(name, n):
 def measured_traffic(n):
     """HBM bytes per k_flux launch from the committed counter summary (FETCH_SIZE + WRITE_SIZE,
     each scaled by the copy kernel's reading); None unless taken on the current sources."""
-    d = profile_record("k_flux_2d_1024_counters.md", n)
+    d = profile_record("kernels_2d_1024_counters.md", n)
     return None if d is None else d.get("traffic_bytes_per_launch")
 
 
@@ -126,6 +126,41 @@ def cpu_baseline(workload, size, seed, steps, steps_mt):
     return res
 
 
+WARMSTART = os.path.join(ROOT, "paper_2407_05568_amd", "mlp_warmstart_1024.npz")
+
+
+def learned_speedup(torch, n=1024, seed=2, step=5, tol=1e-8):
+    """The learned warm start against the plain iteration on one frame of a held-out run (the
+    network's weights were trained on other seeds by `python -m paper_2407_05568_amd.learned
+    --size 1024 --save ...`): the redistribution of the state after `step` steps of the method
+    solved to the residual tol by red-black SOR from x^n (plain) and from x^n + the network's
+    displacement (features + inference + 8 Gauss-Seidel sweeps + SOR), and, for reference, from
+    the previous step's converged mesh (not learned).  value = plain time / warm time."""
+    from paper_2407_05568_amd import learned, synth
+    P, meta = learned.load_params(WARMSTART)
+    Pd = torch.from_numpy(P).cuda()
+    p = synth.problem(2, [n, n], bc="outflow")
+    run = learned.Run(torch, p, synth.quadrants_2d(p, synth.quadrant_states(p, seed)), tol)
+    sor = learned.SorSolver(torch, run)
+    run.advance(step - 1)
+    sor.solve(1e-10)
+    xprev = sor.x.clone()
+    run.advance(1)
+    shape = (n, n)
+    feat = torch.empty((2,) + shape, dtype=torch.float32, device="cuda")
+    warm = torch.empty((2,) + shape, dtype=torch.float64, device="cuda")
+    ms_inf = learned.warm_start(torch, run, Pd, feat, warm)
+    sw_w, res_w, ms_w = sor.solve(tol, warm=warm, presmooth=8)
+    sw_p, res_p, ms_p = sor.solve(tol)
+    sw_q, res_q, ms_q = sor.solve(tol, start=xprev)
+    return {"value": ms_p / (ms_w + ms_inf), "unit": "x (plain / warm-started redistribution time)",
+            "plain_ms": ms_p, "warm_ms": ms_w + ms_inf, "inference_ms": ms_inf, "plain_sweeps": sw_p,
+            "warm_sweeps": sw_w, "final_residual": max(res_p, res_w), "tolerance": tol,
+            "previous_mesh_speedup": ms_p / ms_q,
+            "sample": "seed %d (held out), state after %d steps of the %dx%d quadrant run; weights trained on "
+                      "seeds %s" % (seed, step, n, n, meta.get("train_seeds"))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +173,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-size", type=int, default=None)
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--no-learned", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the solver runs on one GPU (several would split the grid into slabs with halo "
@@ -241,6 +277,11 @@ def main():
         roofline["frac_in_step"] = None if t_in is None else FLOPS_PER_IFACE_2D * nif / (t_in * 1e-6) / PEAK_FP64
     roofline["flops_per_interface"] = FLOPS_PER_IFACE_3D if three else FLOPS_PER_IFACE_2D
 
+    learned = None
+    if not three and not args.no_learned and n == 1024:
+        print("learned warm start ...", file=sys.stderr, flush=True)
+        learned = learned_speedup(torch)
+
     cpu = None
     if not args.no_cpu:
         print("cpu baseline ...", file=sys.stderr, flush=True)
@@ -273,6 +314,7 @@ def main():
         "config": cfg,
         "rhs_only": rhs_only,
         "roofline": roofline,
+        "learned_speedup": learned,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

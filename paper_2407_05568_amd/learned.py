@@ -4,19 +4,27 @@ the comparison with the plain iteration at the same final residual.
 
 A frame is a state (U^n, x^n) of a moving-mesh run of the method (its usual fixed sweep
 count): its inputs are the node features written by ``mlp_features`` and its target is the
-converged (pre-limiter) displacement (x^[mu] - x^n) / dxi per component of the redistribution
-of that state solved to the tolerance mesh_tol.  The
-network sees only the 5 x 5 stencil of features around a node; the plain Jacobi iteration
-always finishes the solve from x^n + warm_dx to the same tolerance, so the final mesh
-residual does not depend on the network.
+converged (pre-limiter) displacement (x* - x^n) / dxi per component, x* the solution of the
+discretised mesh equations for the monitor of that state.  The network sees only the 5 x 5
+stencil of features around a node.
+
+Every solve is finished by a plain iteration to the same final residual (the largest node
+update one Jacobi sweep would make), so the final mesh residual does not depend on the
+network.  Two finishers: the method's Jacobi iteration (tolerance mode of redistribute_mesh)
+and red-black SOR (`mesh_sor`, Gauss-Seidel for relax 1).  The SOR comparison starts the warm
+solve with a few Gauss-Seidel sweeps, which damp the pointwise error of the network's output
+(over-relaxed SOR damps every mode at the same slow rate, so pointwise noise would otherwise
+cost as many sweeps as a smooth error of the same size).
 
 Run as a module for the full-size experiment (prints one JSON line, progress on stderr):
-    python -m paper_2407_05568_amd.learned --size 1024
+    python -m paper_2407_05568_amd.learned --size 1024 [--save weights.npz]
 (frames every 5 steps of the method's own runs from 6 training seeds, 3 frames each of 2
 held-out seeds for the comparison).
 """
 import argparse
 import json
+import math
+import os
 import sys
 import time
 
@@ -57,7 +65,7 @@ class Run:
     solves the redistribution of the current state to the tolerance with a second context."""
 
     def __init__(self, torch, p, prim, tol=1e-8, stream=None):
-        self.torch, self.p = torch, p
+        self.torch, self.p, self.tol = torch, p, tol
         self.ctx = Context(p)
         self.ctx_tol = Context(tol_problem(p, tol))
         self.stream = stream or torch.cuda.current_stream()
@@ -108,22 +116,80 @@ class Run:
             raise RuntimeError("scheme raised status flags %d" % st)
 
 
-def generate(torch, p, prims, frames, every, tol=1e-8, tag=""):
+def default_relax(n):
+    """Over-relaxation factor for an n x n grid, 2 / (1 + c pi / n) with c = 0.42, fitted to the
+    best factor of the 64^2 and 128^2 quadrant frames (the variable monitor makes the
+    iteration slower than for the plain Laplacian, whose optimum has c = 1)."""
+    return 2.0 / (1.0 + 0.42 * math.pi / n)
+
+
+class SorSolver:
+    """Red-black SOR to a Jacobi-residual tolerance on the mesh of a `Run`: `check` sweeps at a
+    time, then the largest node update one Jacobi sweep would make is measured; the solve stops
+    once it is below the tolerance (checks included in the time)."""
+
+    def __init__(self, torch, run, relax=None, check=50):
+        self.torch, self.run = torch, run
+        self.relax = relax or default_relax(max(run.p["n"][:2]))
+        self.check = check
+        self.omega = torch.empty_like(run.J)
+        self.x = torch.empty_like(run.x)
+        self.xc = torch.empty_like(run.x)
+        self.res = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+    def residual(self, x):
+        """Largest node update of one Jacobi sweep from x (x is not changed)."""
+        run = self.run
+        self.xc.copy_(x)
+        run.ctx.mesh_jacobi(self.omega, self.xc, 1, self.res, run.stream)
+        return float(self.res.item())
+
+    def solve(self, tol, warm=None, start=None, presmooth=0, max_sweeps=10_000_000):
+        """Solve from x^n (+ warm, a displacement), or from the mesh `start`; `presmooth`
+        Gauss-Seidel sweeps first.  Returns (sweeps, final residual, ms); the mesh is left in
+        self.x."""
+        torch, run = self.torch, self.run
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(run.stream)
+        run.ctx.mesh_monitor(run.JU, run.J, self.omega, run.stream)
+        if start is not None:
+            self.x.copy_(start)
+        elif warm is not None:
+            torch.add(run.x, warm, out=self.x)
+        else:
+            self.x.copy_(run.x)
+        sweeps = 0
+        if presmooth:
+            run.ctx.mesh_sor(self.omega, self.x, presmooth, 1.0, None, run.stream)
+            sweeps += presmooth
+        res = self.residual(self.x)
+        while res >= tol and sweeps < max_sweeps:
+            run.ctx.mesh_sor(self.omega, self.x, self.check, self.relax, None, run.stream)
+            sweeps += self.check
+            res = self.residual(self.x)
+        e1.record(run.stream)
+        torch.cuda.synchronize()
+        return sweeps, res, e0.elapsed_time(e1)
+
+
+def generate(torch, p, prims, frames, every, tol=1e-10, tag=""):
     """Frames from runs of the method: for each initial state in `prims`, `frames` frames taken
-    every `every` steps (features and the converged displacement / dxi, FP32 [F][2][N]).
-    Returns (feats, tgts, per-frame statistics)."""
+    every `every` steps (features and the converged displacement / dxi, FP32 [F][2][N], the
+    mesh equations solved by SOR to the residual tol).  Returns (feats, tgts, statistics)."""
     shape = tuple(reversed(p["n"][:2]))
     F = frames * len(prims)
     feats = torch.empty((F, 2) + shape, dtype=torch.float32, device="cuda")
     tgts = torch.empty_like(feats)
     stats = []
     f = 0
+    d = p["dim"]
     for r, prim in enumerate(prims):
         run = Run(torch, p, prim, tol)
+        sor = SorSolver(torch, run)
         for k in range(frames):
             run.features(feats[f])
-            sw, res, ms = run.solve()
-            run.target(tgts[f])
+            sw, res, ms = sor.solve(tol)
+            tgts[f].copy_(((sor.x - run.x) / run.dxi.view((d,) + (1,) * d)).float())
             stats.append(dict(run=r, frame=k, sweeps=sw, resid=res, ms=ms))
             _log("%srun %d frame %d: %d sweeps, residual %.2e, %.1f ms, |target|max %.2f dxi" % (
                 tag, r, k, sw, res, ms, float(tgts[f].abs().max())))
@@ -172,31 +238,66 @@ def heldout_error(torch, ctx, P, feats, tgts, dxi):
     return (num / den) ** 0.5 if den > 0 else 0.0
 
 
-def compare(torch, run, P, frames, every, tag=""):
-    """At `frames` frames of `run`, `every` steps apart: time the plain solve (x^[0] = x^n) and
-    the warm-started one (features + inference + the same iteration from x^n + warm_dx), both
-    to the tolerance.  The run advances with the method's own step between frames."""
+def warm_start(torch, run, P, feat, warm):
+    """Features and inference for the current state of `run` into warm (2 fields, displacement
+    in domain units); returns the GPU ms they took."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(run.stream)
+    run.features(feat)
+    run.ctx.mlp_infer(feat, P, warm, run.stream)
+    e1.record(run.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def compare(torch, run, P, frames, every, tag="", finisher="sor", presmooth=8, previous=True):
+    """At `frames` frames of `run`, `every` steps apart, the redistribution solved to the
+    tolerance three ways: plain (x^[0] = x^n), warm (features + inference + the same iteration
+    from x^n + warm_dx, with `presmooth` Gauss-Seidel sweeps first for the SOR finisher), and,
+    for the SOR finisher with previous=True, from the converged mesh of the step before (a
+    non-learned warm start, for reference).  finisher "sor" (red-black SOR) or "jacobi" (the
+    method's iteration).  The run advances with the method's own step between frames."""
     shape = tuple(reversed(run.p["n"][:2]))
     feat = torch.empty((2,) + shape, dtype=torch.float32, device="cuda")
     warm = torch.empty((2,) + shape, dtype=torch.float64, device="cuda")
+    sor = SorSolver(torch, run) if finisher == "sor" else None
+    xprev = torch.empty_like(run.x) if (sor and previous) else None
     out = []
     for k in range(frames):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(run.stream)
-        run.features(feat)
-        run.ctx.mlp_infer(feat, P, warm, run.stream)
-        e1.record(run.stream)
-        sw_w, res_w, ms_w = run.solve(warm)
-        torch.cuda.synchronize()
-        ms_inf = e0.elapsed_time(e1)
-        sw_p, res_p, ms_p = run.solve()
+        if xprev is not None:  # the converged mesh of the step before the frame
+            sor.solve(1e-10)
+            xprev.copy_(sor.x)
+            run.advance(1)
+        ms_inf = warm_start(torch, run, P, feat, warm)
+        if sor is not None:
+            tol = run.tol
+            sw_w, res_w, ms_w = sor.solve(tol, warm=warm, presmooth=presmooth)
+            sw_p, res_p, ms_p = sor.solve(tol)
+        else:
+            sw_w, res_w, ms_w = run.solve(warm)
+            sw_p, res_p, ms_p = run.solve()
         rec = dict(plain_sweeps=sw_p, plain_resid=res_p, plain_ms=ms_p, warm_sweeps=sw_w, warm_resid=res_w,
                    warm_ms=ms_w + ms_inf, infer_ms=ms_inf)
+        line = "%sframe %d: plain %d sweeps %.1f ms (res %.1e) | warm %d sweeps %.1f ms (+%.2f ms net, res %.1e)" % (
+            tag, k, sw_p, ms_p, res_p, sw_w, ms_w, ms_inf, res_w)
+        if xprev is not None:
+            sw_q, res_q, ms_q = sor.solve(run.tol, start=xprev)
+            rec.update(prev_sweeps=sw_q, prev_resid=res_q, prev_ms=ms_q)
+            line += " | previous mesh %d sweeps %.1f ms" % (sw_q, ms_q)
         out.append(rec)
-        _log("%sframe %d: plain %d sweeps %.1f ms (res %.1e) | warm %d sweeps %.1f ms (+%.2f ms net, res %.1e)" % (
-            tag, k, sw_p, ms_p, res_p, sw_w, ms_w, ms_inf, res_w))
-        run.advance(every)
+        _log(line)
+        run.advance(every - 1 if xprev is not None else every)
     return out
+
+
+def save_params(path, P, meta):
+    """FP32 parameters and a description of how they were made (npz, no pickled objects)."""
+    np.savez(path, params=P.detach().cpu().numpy().astype(np.float32), meta=np.array(json.dumps(meta)))
+
+
+def load_params(path):
+    d = np.load(path)
+    return d["params"].astype(np.float32), json.loads(str(d["meta"]))
 
 
 def main():
@@ -207,10 +308,13 @@ def main():
     ap.add_argument("--frames", type=int, default=6)
     ap.add_argument("--test-frames", type=int, default=3)
     ap.add_argument("--every", type=int, default=5)
-    ap.add_argument("--iters", type=int, default=3000)
+    ap.add_argument("--iters", type=int, default=20000)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--presmooth", type=int, default=8)
+    ap.add_argument("--jacobi", action="store_true", help="also compare with the Jacobi finisher (slow)")
+    ap.add_argument("--save", default=None, help="write the trained parameters (npz)")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     import torch
@@ -221,28 +325,40 @@ def main():
     tests = [int(v) for v in args.test_seeds.split(",")]
     t0 = time.time()
     prims = [synth.quadrants_2d(p, synth.quadrant_states(p, sd)) for sd in seeds]
-    feats, tgts, gstats = generate(torch, p, prims, args.frames, args.every, args.tol, "train ")
+    feats, tgts, gstats = generate(torch, p, prims, args.frames, args.every, 1e-10, "train ")
     t_gen = time.time() - t0
     ctx = Context(p)
     dxi = torch.tensor([1.0 / n, 1.0 / n], dtype=torch.float64, device="cuda")
     t0 = time.time()
-    P, hist = train(torch, ctx, feats, tgts, args.iters, args.batch, args.lr, seeds[0])
+    P, hist = train(torch, ctx, feats, tgts, args.iters, args.batch, args.lr, seeds[0], log_every=1000)
     torch.cuda.synchronize()
     t_train = time.time() - t0
     err_train = heldout_error(torch, ctx, P, feats, tgts, dxi)
     _log("training frames: relative displacement error %.3f" % err_train)
     del feats, tgts
-    recs = []
-    for sd in tests:
-        run = Run(torch, p, synth.quadrants_2d(p, synth.quadrant_states(p, sd)), args.tol)
-        recs += compare(torch, run, P, args.test_frames, args.every, "held-out seed %d " % sd)
-        del run
-    ps, ws = sum(r["plain_ms"] for r in recs), sum(r["warm_ms"] for r in recs)
+    if args.save:
+        save_params(args.save, P, dict(size=n, train_seeds=seeds, frames=args.frames, every=args.every,
+                                       iters=args.iters, batch=args.batch, lr=args.lr, train_rel_err=err_train,
+                                       command="python -m paper_2407_05568_amd.learned --size %d --iters %d --save PATH" % (n, args.iters)))
     out = dict(size=n, tol=args.tol, train_seeds=seeds, test_seeds=tests, frames_per_run=args.frames,
                every=args.every, iters=args.iters, batch=args.batch, gen_s=t_gen, train_s=t_train, loss=hist,
-               train_rel_err=err_train, plain_ms=ps, warm_ms=ws, speedup=ps / ws if ws > 0 else None,
-               plain_sweeps=sum(r["plain_sweeps"] for r in recs), warm_sweeps=sum(r["warm_sweeps"] for r in recs),
-               max_final_resid=max(max(r["plain_resid"], r["warm_resid"]) for r in recs), frames=recs, gen=gstats)
+               train_rel_err=err_train, presmooth=args.presmooth, gen=gstats)
+    for fin in (["sor", "jacobi"] if args.jacobi else ["sor"]):
+        recs = []
+        for sd in tests:
+            run = Run(torch, p, synth.quadrants_2d(p, synth.quadrant_states(p, sd)), args.tol)
+            recs += compare(torch, run, P, args.test_frames, args.every, "%s held-out seed %d " % (fin, sd), fin,
+                            args.presmooth)
+            del run
+        ps, ws = sum(r["plain_ms"] for r in recs), sum(r["warm_ms"] for r in recs)
+        res = dict(plain_ms=ps, warm_ms=ws, speedup=ps / ws if ws > 0 else None,
+                   plain_sweeps=sum(r["plain_sweeps"] for r in recs), warm_sweeps=sum(r["warm_sweeps"] for r in recs),
+                   max_final_resid=max(max(r["plain_resid"], r["warm_resid"]) for r in recs), frames=recs)
+        if fin == "sor":
+            qs = sum(r["prev_ms"] for r in recs)
+            res.update(previous_ms=qs, previous_speedup=ps / qs if qs > 0 else None,
+                       previous_sweeps=sum(r["prev_sweeps"] for r in recs))
+        out[fin] = res
     line = json.dumps(out)
     print(line, flush=True)
     if args.out:

@@ -19,56 +19,14 @@ comparison: held-out initial states, taken every 5 steps of the method's own run
 """
 import argparse
 import json
-import math
 import sys
 
 from . import synth
-from .learned import Run
+from .learned import Run, SorSolver, default_relax
 
 
 def _log(*a):
     print(*a, file=sys.stderr, flush=True)
-
-
-def default_relax(n):
-    """Over-relaxation factor for an n x n grid, 2 / (1 + c pi / n) with c = 0.42, fitted to the
-    best factor of the 64^2 and 128^2 quadrant frames (the variable monitor makes the
-    iteration slower than for the plain Laplacian, whose optimum has c = 1)."""
-    return 2.0 / (1.0 + 0.42 * math.pi / n)
-
-
-class SorSolver:
-    """Red-black SOR to a Jacobi-residual tolerance on the mesh of a `Run`."""
-
-    def __init__(self, torch, run, relax, check=50):
-        self.torch, self.run, self.relax, self.check = torch, run, relax, check
-        self.omega = torch.empty_like(run.J)
-        self.x = torch.empty_like(run.x)
-        self.xc = torch.empty_like(run.x)
-        self.res = torch.zeros(1, dtype=torch.float64, device="cuda")
-
-    def residual(self, x):
-        """Largest node update of one Jacobi sweep from x (x is not changed)."""
-        run = self.run
-        self.xc.copy_(x)
-        run.ctx.mesh_jacobi(self.omega, self.xc, 1, self.res, run.stream)
-        return float(self.res.item())
-
-    def solve(self, tol, max_sweeps=10_000_000):
-        """Returns (sweeps, final residual, ms) of a solve from x^n; the mesh is left in self.x."""
-        torch, run = self.torch, self.run
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(run.stream)
-        run.ctx.mesh_monitor(run.JU, run.J, self.omega, run.stream)
-        self.x.copy_(run.x)
-        sweeps, res = 0, math.inf
-        while res >= tol and sweeps < max_sweeps:
-            run.ctx.mesh_sor(self.omega, self.x, self.check, self.relax, None, run.stream)
-            sweeps += self.check
-            res = self.residual(self.x)
-        e1.record(run.stream)
-        torch.cuda.synchronize()
-        return sweeps, res, e0.elapsed_time(e1)
 
 
 def compare(torch, run, frames, every, relax, tol, check, tag=""):
