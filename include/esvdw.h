@@ -84,7 +84,9 @@ typedef struct esvdw_ctx esvdw_ctx;
 
 /* Validates the parameters and allocates the context's scratch on the current device.
  * Ownership of *out passes to the caller (release with esvdw_destroy).  EINVAL on bad
- * parameters, EHIP on allocation failure. */
+ * parameters (among them a grid whose padded node count, with 3 ghost layers per side and the
+ * x rows rounded up to 16, reaches 2^29: the kernels address a field with 32-bit byte offsets),
+ * EHIP on allocation failure. */
 int esvdw_create(const esvdw_params *p, esvdw_ctx **out);
 void esvdw_destroy(esvdw_ctx *ctx);
 

@@ -22,6 +22,14 @@ int params_valid(const esvdw_params *p) {
   if (!(p->cfl > 0.0) && !(p->dt_fixed > 0.0)) return 0;
   if (p->monitor_kind != ESVDW_MON_VDW && p->monitor_kind != ESVDW_MON_SINE) return 0;
   if (p->kappa < 0 || p->kappa > 2 || p->n_filter < 0 || p->mu < 0) return 0;
+  // the flux kernels address a field of the padded node buffer with 32-bit byte offsets
+  double pn = 1.0;
+  for (int k = 0; k < p->dim; ++k) {
+    long pk = (long)p->n[k] + 2 * GH;
+    if (k == 0) pk = (pk + 15) & ~15L;
+    pn *= (double)pk;
+  }
+  if (pn * 8.0 >= 4294967296.0) return 0;
   return 1;
 }
 
@@ -56,6 +64,8 @@ void make_geo(const esvdw_params *p, Geo *G) {
   G->b = p->b;
   G->delta = p->R / p->cv;
   G->iR = 1.0 / p->R;
+  for (int k = 0; k < 7; ++k) G->lmc[k] = 1.0 / (15 - 2 * k);
+  G->lmc[7] = 1.0 / 17;
   G->wl0 = p->weno_lin[0];
   G->wl1 = p->weno_lin[1];
   G->wl2 = p->weno_lin[2];

@@ -25,6 +25,7 @@ struct Geo {
   double R, cv, a, b, delta, iR;
   double wl0, wl1, wl2, weps, iwl0;
   int diss;
+  double lmc[8];  // log-mean series coefficients 1/15, 1/13, ..., 1/3, 1/17 (see inv_logmean_rn)
 };
 
 // sixth-order central / high-order flux coefficients alpha_{3,m}: sum m a = 1, sum m^3 a = sum m^5 a = 0
@@ -43,6 +44,23 @@ __device__ __forceinline__ double rcp_nr(double x) {
   r = fma(r, e, r);
   e = fma(-x, r, 1.0);
   return fma(r, e, r);
+}
+
+// sqrt(x) for the flux kernels, x > 0 normal and finite: the hardware estimate y of 1/sqrt(x)
+// refined by the coupled Newton iteration for g = sqrt(x) and h = 1/(2 sqrt(x)) (Markstein's
+// method: r = 1/2 - g h, g += g r, h += h r), then two corrections g += (x - g^2) h.  The
+// library square root adds range scaling and special cases that the kernels' positive
+// thermodynamic and metric magnitudes do not need.
+__device__ __forceinline__ double sqrt_nr(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
 }
 
 __device__ __forceinline__ int floordiv(int i, int n) { return i >= 0 ? i / n : -((-i + n - 1) / n); }
@@ -295,53 +313,43 @@ __device__ __forceinline__ bool admissible(const Geo &G, double rho, double T) {
   return ok && (G.R * T - 2.0 * G.a * rho * ob * ob > 0.0);
 }
 
-// logarithmic mean (a_r - a_l)/(ln a_r - ln a_l) = (a_l + a_r)/(2 atanh(f)/f), f = (a_r - a_l)/(a_r + a_l);
-// atanh(f)/f by its Taylor series when f^2 < 1e-4, else by log1p.
-__device__ __forceinline__ double logmean(double al, double ar) {
-  double s = al + ar;
-  double f = (ar - al) / s;
-  double u = f * f;
-  double h;
-  if (u < 1e-4) {
-    h = 1.0 + u * (1.0 / 3.0 + u * (1.0 / 5.0 + u * (1.0 / 7.0 + u * (1.0 / 9.0))));
-  } else {
-    h = 0.5 * log1p(2.0 * f / (1.0 - f)) / f;
-  }
-  return 0.5 * s / h;
-}
-
 // 1/L(a_l, a_r) for the logarithmic mean L = (a_r - a_l)/(ln a_r - ln a_l), given the node
-// logarithms la = ln a_l, lb = ln a_r.  Close arguments (|a_r - a_l| < 0.1 (a_l + a_r), i.e.
-// f = (a_r - a_l)/(a_r + a_l) with f^2 < 0.01) use 1/L = 2 (atanh(f)/f)/(a_l + a_r) with
-// the Taylor series of atanh(f)/f to u^8 (truncation < 1e-17); otherwise the logarithms.
-__device__ __forceinline__ double inv_logmean(double al, double ar, double la, double lb) {
-  double d = ar - al, s = al + ar;
-  if (fabs(d) < 0.1 * s) {
-    double is = 1.0 / s;
-    double f = d * is, u = f * f;
-    double h = 1.0 + u * (1.0 / 3 + u * (1.0 / 5 + u * (1.0 / 7 + u * (1.0 / 9 + u * (1.0 / 11 + u * (1.0 / 13 +
-               u * (1.0 / 15 + u * (1.0 / 17))))))));
-    return 2.0 * h * is;
-  }
-  return (lb - la) / d;
-}
-
-// The same 1/L(al, ar) with the reciprocal of its denominator supplied, so that several
-// log means can share one division: den = logmean_den(al, ar) is the sum (near al = ar, where
-// the series in ((ar - al)/(ar + al))^2 is used) or the difference.
+// logarithms.  Close arguments (|a_r - a_l| < 0.1 (a_l + a_r), i.e. f = (a_r - a_l)/(a_r + a_l)
+// with f^2 < 0.01) use 1/L = 2 (atanh(f)/f)/(a_l + a_r) with the Taylor series of atanh(f)/f to
+// u^8, u = f^2 (truncation < 1e-17); otherwise the logarithms.  The reciprocal of the
+// denominator is supplied, so that several log means can share one division:
+// den = logmean_den(al, ar) is the sum (series) or the difference (logarithms).
 __device__ __forceinline__ double logmean_den(double al, double ar) {
   double d = ar - al, s = al + ar;
   return fabs(d) < 0.1 * s ? s : d;
 }
-__device__ __forceinline__ double inv_logmean_r(double al, double ar, double la, double lb, double iden) {
-  double d = ar - al, s = al + ar;
-  if (fabs(d) < 0.1 * s) {
-    double f = d * iden, u = f * f;
-    double h = 1.0 + u * (1.0 / 3 + u * (1.0 / 5 + u * (1.0 / 7 + u * (1.0 / 9 + u * (1.0 / 11 + u * (1.0 / 13 +
-               u * (1.0 / 15 + u * (1.0 / 17))))))));
-    return 2.0 * h * iden;
+
+// N values 1/L(al_j, ar_j) with la_j = ln al_j, lb_j = ln ar_j and iden_j = 1/logmean_den,
+// the N series evaluated side by side.  cf: 1/15, 1/13, ..., 1/3 and 1/17 (Geo::lmc: passed as
+// uniform values, so that the FMAs read them from scalar registers; a 64-bit literal cannot be
+// an FMA operand and would be rebuilt in vector registers at every use).
+template <int N>
+__device__ __forceinline__ void inv_logmean_rn(const double *cf, const double (&al)[N], const double (&ar)[N],
+                                               const double (&la)[N], const double (&lb)[N], const double (&iden)[N],
+                                               double (&out)[N]) {
+  double u[N], h[N];
+  bool ser[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const double d = ar[j] - al[j], s = al[j] + ar[j], f = d * iden[j];
+    ser[j] = fabs(d) < 0.1 * s;
+    u[j] = f * f;
+    h[j] = cf[7];
   }
-  return (lb - la) * iden;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) h[j] = fma(u[j], h[j], cf[k]);
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) h[j] = fma(u[j], h[j], 1.0);
+#pragma unroll
+  for (int j = 0; j < N; ++j) out[j] = ser[j] ? 2.0 * h[j] * iden[j] : (lb[j] - la[j]) * iden[j];
 }
 
 // Multi-resolution WENO, fifth order: left limit at the right face of the centre cell of
@@ -373,31 +381,39 @@ __device__ __forceinline__ double mrweno5(const Geo &G, double a, double b, doub
   return (w5 * top + w3 * q3 + w1 * c) / (w5 + w3 + w1);
 }
 
-// mrweno5 as a fraction num / den with den > 0 (the caller divides, possibly sharing the division)
-__device__ __forceinline__ void mrweno5_frac(const Geo &G, double a, double b, double c, double d, double e, double &num,
-                                             double &den) {
-  double q5 = (2.0 * a - 13.0 * b + 47.0 * c + 27.0 * d - 3.0 * e) * (1.0 / 60.0);
-  double q3 = (-b + 5.0 * c + 2.0 * d) * (1.0 / 6.0);
-  double dl = c - b, dr = d - c;
-  double s1 = fmin(dl * dl, dr * dr);
-  double t1 = b - 2.0 * c + d, t2 = d - b;
-  double s3 = (13.0 / 12.0) * t1 * t1 + 0.25 * t2 * t2;
-  // the Jiang-Shu functional of the quartic depends only on its derivatives, so it is evaluated
-  // on the data relative to the centre value c: the same quadratic form without cancellation
-  // between terms of the size of the data's square (entropy-variable data carry c_v ln T offsets)
+// mrweno5 relative to the centre value, as a fraction: mrweno5(a, b, c, d, e) = c + num / den
+// with den > 0 (the caller divides, possibly sharing the division).  Every level is formed
+// from the differences to c (the levels' coefficients sum to one, and the 1-point level is c
+// itself), which also removes the cancellation of c in the weighted sum.  The weights are
+// those of mrweno5 multiplied through by (s5 + eps)(s3 + eps)(s1 + eps): with e_l = s_l + eps
+// and P = e5 e3 e1, w_l = wl_l (P + tau P / e_l); the linear weights then cancel from the
+// quartic level's numerator, w5 (q5 - wl1 q3 - wl2 c)/wl0 = (P + tau e3 e1)(q5 - wl1 q3 - wl2 c).
+__device__ __forceinline__ void mrweno5_cfrac(const Geo &G, double a, double b, double c, double d, double e,
+                                              double &num, double &den) {
   const double am = a - c, bm = b - c, dp = d - c, ep = e - c;
-  double s5 = (104963.0 * (bm * bm + dp * dp) - 51001.0 * (am * bm + dp * ep) + 179098.0 * bm * dp -
-               38947.0 * (bm * ep + am * dp) + 6908.0 * (am * am + ep * ep) + 8209.0 * am * ep) *
-              (1.0 / 5040.0);
-  double tt = 0.5 * (fabs(s5 - s1) + fabs(s5 - s3));
-  double tau = tt * tt;
-  double e5 = s5 + G.weps, e3 = s3 + G.weps, e1 = s1 + G.weps;
-  double w5 = G.wl0 * (e3 * e1) * (e5 + tau);
-  double w3 = G.wl1 * (e5 * e1) * (e3 + tau);
-  double w1 = G.wl2 * (e5 * e3) * (e1 + tau);
-  double top = (q5 - G.wl1 * q3 - G.wl2 * c) * G.iwl0;
-  num = w5 * top + w3 * q3 + w1 * c;
-  den = w5 + w3 + w1;
+  const double q5 = (2.0 / 60.0) * am - (13.0 / 60.0) * bm + (27.0 / 60.0) * dp - (3.0 / 60.0) * ep;
+  const double q3 = (1.0 / 3.0) * dp - (1.0 / 6.0) * bm;
+  const double b2 = bm * bm, d2 = dp * dp, t0 = b2 + d2;
+  const double s1 = fmin(b2, d2);
+  // (13/12)(bm + dp)^2 + (1/4)(dp - bm)^2
+  const double s3 = fma((5.0 / 3.0) * bm, dp, (4.0 / 3.0) * t0);
+  // the Jiang-Shu functional of the quartic (see mrweno5), grouped by the first factor:
+  // c1 (bm^2 + dp^2) + bm (-c2 am + c3 dp - c4 ep) - dp (c2 ep + c4 am) + am (c5 am + c6 ep) + c5 ep^2
+  const double X = fma(179098.0 / 5040.0, dp, fma(-38947.0 / 5040.0, ep, (-51001.0 / 5040.0) * am));
+  const double Y = fma(-51001.0 / 5040.0, ep, (-38947.0 / 5040.0) * am);
+  const double Z = fma(8209.0 / 5040.0, ep, (6908.0 / 5040.0) * am);
+  double s5 = fma(bm, X, (104963.0 / 5040.0) * t0);
+  s5 = fma(dp, Y, s5);
+  s5 = fma(am, Z, s5);
+  s5 = fma(ep, (6908.0 / 5040.0) * ep, s5);
+  const double tt = 0.5 * (fabs(s5 - s1) + fabs(s5 - s3));
+  const double tau = tt * tt;
+  const double e5 = s5 + G.weps, e3 = s3 + G.weps, e1 = s1 + G.weps;
+  const double e31 = e3 * e1, P = e5 * e31;
+  const double A5 = fma(e31, tau, P), A3 = fma(e5 * e1, tau, P), A1 = fma(e5 * e3, tau, P);
+  const double wq3 = G.wl1 * q3;
+  num = fma(A5, q5 - wq3, A3 * wq3);
+  den = fma(G.wl0, A5, fma(G.wl1, A3, G.wl2 * A1));
 }
 
 // ---------------------------------------------------------------------------------

@@ -201,18 +201,20 @@ __global__ void __launch_bounds__(256, 3) k_flux(Geo G, const double *__restrict
                                               unsigned *flags) {
   using TL = Tile<D, K>;
   __shared__ double sP[FluxLds<D, K, TL::X, TL::Y, TL::Z>::SIZE];
-  flux_tile<D, K, TL::X, TL::Y, TL::Z>(G, nd, Fo, nif, flags, blockIdx.x * TL::X, blockIdx.y * TL::Y,
-                                       blockIdx.z * TL::Z, sP);
+  flux_tile<D, K, TL::X, TL::Y, TL::Z, TL::PX, TL::PY>(G, nd, Fo, nif, flags, blockIdx.x * TL::X, blockIdx.y * TL::Y,
+                                                       blockIdx.z * TL::Z, sP);
 }
 
 // =============================== update ==========================================
 
-// 2D: the direction-0 interface fluxes of a 64 x 4 tile and the update of the 63 x 4 nodes
-// between them, in one kernel (the direction-1 fluxes are read from their buffer).  Tiles step
-// by 63 nodes along x, so the tile's last interface is also computed by the next tile; in
-// exchange the direction-0 fluxes never go through memory and the separate update kernel is
-// not needed.  The node's sums are those of update_point (direction 0, then direction 1).
-#define FU_TX 64
+// 2D: the direction-0 interface fluxes of a 62 x 4 tile (rows of 64 threads, so that the
+// pair-flux items are one per thread) and the update of the 61 x 4 nodes between them, in one
+// kernel (the direction-1 fluxes are read from their buffer).  Tiles step by 61 nodes along x,
+// so the tile's last interface is also computed by the next tile; in exchange the direction-0
+// fluxes never go through memory and the separate update kernel is not needed.  The node's
+// sums are those of update_point (direction 0, then direction 1).
+#define FU_TX 62
+#define FU_PX 64
 #define FU_TY 4
 __global__ void __launch_bounds__(256, 3)
     k_flux_upd2(Geo G, const double *__restrict__ nd, const double *__restrict__ F1, long nif1, int mode, int s,
@@ -225,9 +227,9 @@ __global__ void __launch_bounds__(256, 3)
   const int bx0 = blockIdx.x * (FU_TX - 1), by0 = blockIdx.y * FU_TY;
   double Fl[5];
   int a0, a1, a2;
-  const bool ok = flux_tile_eval<2, 0, FU_TX, FU_TY, 1>(G, nd, flags, bx0, by0, 0, sP, Fl, a0, a1, a2);
+  const bool ok = flux_tile_eval<2, 0, FU_TX, FU_TY, 1, FU_PX>(G, nd, flags, bx0, by0, 0, sP, Fl, a0, a1, a2);
   __syncthreads();  // every thread has read its pair fluxes
-  const int tid = threadIdx.x, tx = tid % FU_TX, ty = tid / FU_TX;
+  const int tid = threadIdx.x, tx = tid % FU_PX, ty = tid / FU_PX;
   if (ok) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) sP[c * 256 + tid] = Fl[c];

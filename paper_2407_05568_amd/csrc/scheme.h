@@ -152,35 +152,47 @@ __device__ __forceinline__ void node_point(const Geo &G, const double *__restric
 // each thread combines the six pair fluxes of its interface with alpha_m (eq.
 // ECFlux_curv_2p) and subtracts the dissipation of eq. HOstable.
 
+// Tile<D, K>: X x Y x Z interfaces per 256-thread block, threads in rows of PX (PX >= X; lanes
+// tx >= X of a row have no interface).  The x tiles compute 62 interfaces per row of 64
+// threads so that the pair-flux items (X + 2 per row) are exactly one per thread.
 template <int D, int K> struct Tile;
-template <> struct Tile<1, 0> { static constexpr int X = 256, Y = 1, Z = 1; };
-template <> struct Tile<2, 0> { static constexpr int X = 64, Y = 4, Z = 1; };
-template <> struct Tile<2, 1> { static constexpr int X = 16, Y = 16, Z = 1; };
-template <> struct Tile<3, 0> { static constexpr int X = 64, Y = 4, Z = 1; };
-template <> struct Tile<3, 1> { static constexpr int X = 16, Y = 16, Z = 1; };
-template <> struct Tile<3, 2> { static constexpr int X = 16, Y = 4, Z = 4; };
+template <> struct Tile<1, 0> { static constexpr int X = 256, Y = 1, Z = 1, PX = X, PY = Y; };
+template <> struct Tile<2, 0> { static constexpr int X = 62, Y = 4, Z = 1, PX = 64, PY = Y; };
+template <> struct Tile<2, 1> { static constexpr int X = 16, Y = 16, Z = 1, PX = X, PY = Y; };
+template <> struct Tile<3, 0> { static constexpr int X = 62, Y = 4, Z = 1, PX = 64, PY = Y; };
+template <> struct Tile<3, 1> { static constexpr int X = 16, Y = 16, Z = 1, PX = X, PY = Y; };
+template <> struct Tile<3, 2> { static constexpr int X = 16, Y = 4, Z = 4, PX = X, PY = Y; };
 
 // node data used by a pair flux (direction K)
 template <int D> struct Pq {
   double rho, v[D], T, iT, g, iob, lr, lb, lt, m[D], mt;
 };
 
+// Field f of the node buffer at the byte offset ob of a node.  The field's base address is the
+// same for every lane and the lane's offset is 32 bits wide, so the load takes the form with a
+// scalar base and a 32-bit vector offset: no 64-bit address arithmetic per lane and field.
+// Needs 8 PN < 2^32, which esvdw_create checks.
+__device__ __forceinline__ double ndf(const Geo &G, const double *__restrict__ nd, int f, unsigned ob) {
+  const char *base = reinterpret_cast<const char *>(nd + (long)f * G.PN);
+  return *reinterpret_cast<const double *>(base + ob);
+}
+
 template <int D, int K>
-__device__ __forceinline__ void load_pq(const Geo &G, const double *__restrict__ nd, long t, Pq<D> &q) {
+__device__ __forceinline__ void load_pq(const Geo &G, const double *__restrict__ nd, unsigned ob, Pq<D> &q) {
   using F = NF_<D>;
-  q.rho = nd[F::RHO * G.PN + t];
+  q.rho = ndf(G, nd, F::RHO, ob);
 #pragma unroll
-  for (int m = 0; m < D; ++m) q.v[m] = nd[(long)(F::V + m) * G.PN + t];
-  q.T = nd[F::T * G.PN + t];
-  q.iT = nd[F::IT * G.PN + t];
-  q.iob = nd[F::IOB * G.PN + t];
+  for (int m = 0; m < D; ++m) q.v[m] = ndf(G, nd, F::V + m, ob);
+  q.T = ndf(G, nd, F::T, ob);
+  q.iT = ndf(G, nd, F::IT, ob);
+  q.iob = ndf(G, nd, F::IOB, ob);
   q.g = G.R * q.iob - G.a * q.rho * q.iT;  // g = R/(1 - b rho) - a rho/T
-  q.lr = nd[F::LNR * G.PN + t];
-  q.lb = nd[F::LNB * G.PN + t];
-  q.lt = nd[F::LNT * G.PN + t];
+  q.lr = ndf(G, nd, F::LNR, ob);
+  q.lb = ndf(G, nd, F::LNB, ob);
+  q.lt = ndf(G, nd, F::LNT, ob);
 #pragma unroll
-  for (int j = 0; j < D; ++j) q.m[j] = nd[(long)(F::MS + K * D + j) * G.PN + t];
-  q.mt = nd[(long)(F::XS + K) * G.PN + t];
+  for (int j = 0; j < D; ++j) q.m[j] = ndf(G, nd, F::MS + K * D + j, ob);
+  q.mt = ndf(G, nd, F::XS + K, ob);
 }
 
 // Two-point EC flux (eq. ECfluxMM with the closed-form U~, F~_j of Section 3.1), written in
@@ -189,50 +201,60 @@ __device__ __forceinline__ void load_pq(const Geo &G, const double *__restrict__
 //   F_E = ({v/T}.F_v - K F_rho + a {rho u}{rho/T})/{1/T},
 // D = R/L(rho) + R b/L(1 - b rho) + R b/Pi - 2a/{T}, A = R b/Pi - a/{T},
 // K = {|v|^2/T}/2 - c_v {T}/L(T) + 2a{rho/T}; out[nv] receives {J dxi/dt}.
+// The means are carried as sums (S x = x_l + x_r = 2{x}, with ul2 = 2u per node) and the
+// factors 1/2 collected into a few constants: F_rho = (S(rho u2) A + S g S u2 / 2) / (4D),
+// F_v = (S v F_rho + S m pt) / 2 with pt = S rho S T S g / 8, and with K4 = 4K,
+// F_E = (S(v/T).F_v - K4 F_rho / 2 + a S(rho u2) S(rho/T) / 4) / S(1/T) (one shared division by
+// D S(1/T) gives both 1/D and 1/{1/T}).
 template <int D>
 __device__ __forceinline__ void ec_pair(const Geo &G, const Pq<D> &l, const Pq<D> &r, double *out, unsigned &bad) {
-  double mb[D];
+  double Sm[D];
 #pragma unroll
-  for (int j = 0; j < D; ++j) mb[j] = 0.5 * (l.m[j] + r.m[j]);
-  double mbt = 0.5 * (l.mt + r.mt);
-  double ul = mbt, ur = mbt;
+  for (int j = 0; j < D; ++j) Sm[j] = l.m[j] + r.m[j];
+  const double Smt = l.mt + r.mt;
+  double ul2 = Smt, ur2 = Smt;
 #pragma unroll
   for (int j = 0; j < D; ++j) {
-    ul += mb[j] * l.v[j];
-    ur += mb[j] * r.v[j];
+    ul2 = fma(Sm[j], l.v[j], ul2);
+    ur2 = fma(Sm[j], r.v[j], ur2);
   }
-  double rhom = 0.5 * (l.rho + r.rho), Tm = 0.5 * (l.T + r.T), iTm = 0.5 * (l.iT + r.iT);
-  double rTm = 0.5 * (l.rho * l.iT + r.rho * r.iT), gm = 0.5 * (l.g + r.g);
-  double rum = 0.5 * (l.rho * ul + r.rho * ur), um = 0.5 * (ul + ur);
-  double Rb_Pi = G.R * G.b * l.iob * r.iob;
+  const double SiT = l.iT + r.iT, SrT = fma(l.rho, l.iT, r.rho * r.iT), Sg = l.g + r.g, Sr = l.rho + r.rho;
+  const double Sru = fma(l.rho, ul2, r.rho * ur2), Su = ul2 + ur2;
+  const double Rb_Pi = G.R * G.b * l.iob * r.iob;
   // the denominators of 1/L(rho), 1/L(1 - b rho), 1/L(T) and of the mean 1/{T} share one division
   const double obl = 1.0 - G.b * l.rho, obr = 1.0 - G.b * r.rho;
   const double dR = logmean_den(l.rho, r.rho), dB = logmean_den(obl, obr), dT = logmean_den(l.T, r.T);
   const double sT = l.T + r.T;
   const double t1 = dR * dB, t2 = dT * sT, rq = rcp_nr(t1 * t2), r1 = rq * t2, r2 = rq * t1;
-  double iTmean = 2.0 * (r2 * dT);
-  double Dd = G.R * inv_logmean_r(l.rho, r.rho, l.lr, r.lr, r1 * dB) + Rb_Pi - 2.0 * G.a * iTmean;
-  if (G.b > 0.0) Dd += G.R * G.b * inv_logmean_r(obl, obr, l.lb, r.lb, r1 * dR);
-  double A = Rb_Pi - G.a * iTmean;
-  double v2T = 0.0;
-#pragma unroll
-  for (int m = 0; m < D; ++m) v2T += l.v[m] * l.v[m] * l.iT + r.v[m] * r.v[m] * r.iT;
-  double Kk = 0.25 * v2T - G.cv * Tm * inv_logmean_r(l.T, r.T, l.lt, r.lt, r2 * sT) + 2.0 * G.a * rTm;
-  if (!(Dd > 0.0)) bad = 1u;
-  // and the two final divisions (by D and by {1/T}) share another
-  const double rd = rcp_nr(Dd * iTm);
-  double Fr = (rum * A + gm * um) * (rd * iTm);
-  double pt = rhom * Tm * gm;
-  double sum = 0.0;
+  const double iTmean = 2.0 * (r2 * dT);
+  // 1/L(rho), 1/L(1 - b rho), 1/L(T) (the second is multiplied by b = 0 without a covolume)
+  double il[3];
+  inv_logmean_rn<3>(G.lmc, {l.rho, obl, l.T}, {r.rho, obr, r.T}, {l.lr, l.lb, l.lt}, {r.lr, r.lb, r.lt},
+                    {r1 * dB, r1 * dR, r2 * sT}, il);
+  const double Dd = G.R * il[0] + Rb_Pi - 2.0 * G.a * iTmean + G.R * G.b * il[1];
+  const double A = Rb_Pi - G.a * iTmean;
+  double vTl[D], vTr[D], Sv2T = 0.0;
 #pragma unroll
   for (int m = 0; m < D; ++m) {
-    double Fv = 0.5 * (l.v[m] + r.v[m]) * Fr + mb[m] * pt;
+    vTl[m] = l.v[m] * l.iT;
+    vTr[m] = r.v[m] * r.iT;
+    Sv2T = fma(l.v[m], vTl[m], fma(r.v[m], vTr[m], Sv2T));
+  }
+  const double K4 = Sv2T - 2.0 * G.cv * sT * il[2] + 4.0 * G.a * SrT;
+  if (!(Dd > 0.0)) bad = 1u;
+  const double rd = rcp_nr(Dd * SiT);
+  const double Fr = 0.25 * fma(Sru, A, 0.5 * (Sg * Su)) * (rd * SiT);
+  const double Fh = 0.5 * Fr, ph = 0.0625 * (Sr * sT * Sg);
+  double sumS = 0.0;
+#pragma unroll
+  for (int m = 0; m < D; ++m) {
+    const double Fv = fma(l.v[m] + r.v[m], Fh, Sm[m] * ph);
     out[1 + m] = Fv;
-    sum += 0.5 * (l.v[m] * l.iT + r.v[m] * r.iT) * Fv;
+    sumS = fma(vTl[m] + vTr[m], Fv, sumS);
   }
   out[0] = Fr;
-  out[D + 1] = (sum - Kk * Fr + G.a * rum * rTm) * (rd * Dd);
-  out[D + 2] = mbt;
+  out[D + 1] = (fma(-K4, Fh, sumS) + 0.25 * G.a * Sru * SrT) * (rd * Dd);
+  out[D + 2] = 0.5 * Smt;
 }
 
 // interface eigen-system in the rotated frame
@@ -303,15 +325,17 @@ template <int D, int K, int TX, int TY, int TZ> struct FluxLds {
 
 // One 256-thread block computes the interface fluxes of the tile whose first interface is
 // (bx0, by0, bz0): this thread's interface (a0, a1, a2) into Fl (nv + 1 values: the ES flux and
-// the GCL flux of J dxi_K/dt); false if the thread has no interface.  sP: FluxLds<...>::SIZE
-// doubles of LDS.  Every thread reaches the internal barrier.
-template <int D, int K, int TX, int TY, int TZ>
+// the GCL flux of J dxi_K/dt); false if the thread has no interface.  The threads form a
+// PX x PY x TZ block, PX >= TX, PY >= TY (threads outside TX x TY x TZ have no interface).
+// sP: FluxLds<...>::SIZE doubles of LDS.
+// Every thread reaches the internal barrier.
+template <int D, int K, int TX, int TY, int TZ, int PX = TX, int PY = TY>
 __device__ __forceinline__ bool flux_tile_eval(const Geo &G, const double *__restrict__ nd, unsigned *flags, int bx0,
                                                int by0, int bz0, double *__restrict__ sP, double (&Fl)[D + 3],
                                                int &a0, int &a1, int &a2) {
   using F = NF_<D>;
-  static_assert(TX * TY * TZ == 256, "flux tiles map one interface to each of 256 threads");
-  using TL = TileShape<TX, TY, TZ>;
+  static_assert(PX >= TX && PY >= TY && PX * PY * TZ == 256, "flux tiles map at most one interface to each of 256 threads");
+  using TL = TileShape<PX, PY, TZ>;
   constexpr int NV = D + 2, NC = NV + 1;
   using LQ = FluxLds<D, K, TX, TY, TZ>;
   constexpr int QX = LQ::QX, QY = LQ::QY;
@@ -323,23 +347,81 @@ __device__ __forceinline__ bool flux_tile_eval(const Geo &G, const double *__res
   unsigned bad = 0;
 
   // ---- phase 1: pair fluxes of the nodes owning pairs of this tile ----
-  for (int q = tid; q < Q; q += 256) {
-    int qx = q % QX, qy = (q / QX) % QY, qz = q / (QX * QY);
-    // node index: along K the first item is the node two below the tile's first left node
-    int i0 = bx0 + qx - (K == 0 ? 3 : 0), i1 = by0 + qy - (K == 1 ? 3 : 0), i2 = bz0 + qz - (K == 2 ? 3 : 0);
-    int ik = K == 0 ? i0 : (K == 1 ? i1 : i2);
-    bool ok = ik <= G.n[K] - 1 && (K == 0 || i0 < G.n[0]) && (K == 1 || i1 < G.n[1]) && (K == 2 || i2 < G.n[2]);
-    if (!ok) continue;
-    long pt = ((long)(i2 + G.g[2]) * G.P[1] + (i1 + G.g[1])) * G.P[0] + (i0 + G.g[0]);
-    Pq<D> a, b;
-    load_pq<D, K>(G, nd, pt, a);
+  // item q (local coordinates qx, qy, qz); along K the first item is the node two below the
+  // tile's first left node.  Returns false for items whose node lies beyond the grid.
+  auto item_node = [&](int q, unsigned &ob) -> bool {
+    const int qx = q % QX, qy = (q / QX) % QY, qz = q / (QX * QY);
+    const int i0 = bx0 + qx - (K == 0 ? 3 : 0), i1 = by0 + qy - (K == 1 ? 3 : 0), i2 = bz0 + qz - (K == 2 ? 3 : 0);
+    const int ik = K == 0 ? i0 : (K == 1 ? i1 : i2);
+    ob = 8u * (unsigned)(((i2 + G.g[2]) * G.P[1] + (i1 + G.g[1])) * G.P[0] + (i0 + G.g[0]));
+    return ik <= G.n[K] - 1 && (K == 0 || i0 < G.n[0]) && (K == 1 || i1 < G.n[1]) && (K == 2 || i2 < G.n[2]);
+  };
+  // the pair F(node of item q, node m further along K) into its LDS slots
+  auto pair_to_lds = [&](int q, unsigned ob, const Pq<D> &a, int m) {
+    Pq<D> b;
+    load_pq<D, K>(G, nd, ob + 8u * (unsigned)(m * sK), b);
+    double o[NC];
+    ec_pair<D>(G, a, b, o, bad);
 #pragma unroll
-    for (int m = 1; m <= 3; ++m) {
-      load_pq<D, K>(G, nd, pt + m * sK, b);
-      double o[NC];
-      ec_pair<D>(G, a, b, o, bad);
+    for (int c = 0; c < NC; ++c) sP[(c * 3 + (m - 1)) * Q + q] = o[c];
+  };
+  constexpr int QK = K == 0 ? QX : (K == 1 ? QY : LQ::QZ);  // items per line along K
+  constexpr int NL = Q / QK;                                // lines along K
+  if constexpr (Q <= 256 || NL * (QK - 2) != 256) {
+    // every item with all three of its pairs, one item per thread and round
+    for (int q = tid; q < Q; q += 256) {
+      unsigned ob;
+      if (!item_node(q, ob)) continue;
+      Pq<D> a;
+      load_pq<D, K>(G, nd, ob, a);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) sP[(c * 3 + (m - 1)) * Q + q] = o[c];
+      for (int m = 1; m <= 3; ++m) pair_to_lds(q, ob, a, m);
+    }
+  } else {
+    // 256 inner items (k-index >= 2 along K), one per thread with its three pairs; then the
+    // pairs the combination uses from the two low halo items, F(0, 3), F(1, 3) and F(1, 2),
+    // one per thread (the halo items' other pairs are not needed)
+    // (consecutive threads take consecutive nodes along x, for coalesced loads)
+    {
+      int q;
+      if constexpr (K == 0) {
+        q = (tid / (QX - 2)) * QX + 2 + tid % (QX - 2);
+      } else if constexpr (K == 1) {
+        const int r = tid / QX;
+        q = ((r / (QY - 2)) * QY + 2 + r % (QY - 2)) * QX + tid % QX;
+      } else {
+        const int r = tid / QX;
+        q = ((2 + r / QY) * QY + r % QY) * QX + tid % QX;
+      }
+      unsigned ob;
+      if (item_node(q, ob)) {
+        Pq<D> a;
+        load_pq<D, K>(G, nd, ob, a);
+#pragma unroll
+        for (int m = 1; m <= 3; ++m) pair_to_lds(q, ob, a, m);
+      }
+    }
+    for (int u = tid; u < 3 * NL; u += 256) {
+      // unit u: halo item k (0 or 1) of its line along K and the pair m it supplies
+      int q, r;
+      if constexpr (K == 0) {
+        r = u % 3;
+        q = (u / 3) * QX + (r == 0 ? 0 : 1);
+      } else if constexpr (K == 1) {
+        const int w = u / QX;
+        r = w % 3;
+        q = ((w / 3) * QY + (r == 0 ? 0 : 1)) * QX + u % QX;
+      } else {
+        const int w = u / QX;
+        r = w / QY;
+        q = ((r == 0 ? 0 : 1) * QY + w % QY) * QX + u % QX;
+      }
+      const int m = r == 1 ? 2 : 3;
+      unsigned ob;
+      if (!item_node(q, ob)) continue;
+      Pq<D> a;
+      load_pq<D, K>(G, nd, ob, a);
+      pair_to_lds(q, ob, a, m);
     }
   }
   if (G.diss) {
@@ -350,11 +432,11 @@ __device__ __forceinline__ bool flux_tile_eval(const Geo &G, const double *__res
       // the node buffer holds 3 ghost layers: node indices -3 .. n_K + 2 along K
       bool ok = ik <= G.n[K] + 2 && (K == 0 || i0 < G.n[0]) && (K == 1 || i1 < G.n[1]) && (K == 2 || i2 < G.n[2]);
       if (!ok) continue;
-      long pt = ((long)(i2 + G.g[2]) * G.P[1] + (i1 + G.g[1])) * G.P[0] + (i0 + G.g[0]);
-      sV[q] = nd[(long)F::V1 * G.PN + pt];
+      const unsigned ob = 8u * (unsigned)(((i2 + G.g[2]) * G.P[1] + (i1 + G.g[1])) * G.P[0] + (i0 + G.g[0]));
+      sV[q] = ndf(G, nd, F::V1, ob);
 #pragma unroll
-      for (int m = 0; m < D; ++m) sV[(1 + m) * QW + q] = nd[(long)(F::V + m) * G.PN + pt];
-      sV[(D + 1) * QW + q] = nd[(long)F::IT * G.PN + pt];
+      for (int m = 0; m < D; ++m) sV[(1 + m) * QW + q] = ndf(G, nd, F::V + m, ob);
+      sV[(D + 1) * QW + q] = ndf(G, nd, F::IT, ob);
     }
   }
   __syncthreads();
@@ -365,7 +447,7 @@ __device__ __forceinline__ bool flux_tile_eval(const Geo &G, const double *__res
   a1 = by0 + ty;
   a2 = bz0 + tz;
   const int e0 = G.n[0] + (K == 0), e1 = G.n[1] + (K == 1), e2 = G.n[2] + (K == 2);
-  if (a0 >= e0 || a1 >= e1 || a2 >= e2) {
+  if (tx >= TX || ty >= TY || a0 >= e0 || a1 >= e1 || a2 >= e2) {
     if (bad) raise_flag(flags, ESVDW_F_MEANCONSTRAINT);
     return false;
   }
@@ -379,29 +461,31 @@ __device__ __forceinline__ bool flux_tile_eval(const Geo &G, const double *__res
 #pragma unroll
   for (int c = 0; c < NV; ++c) dd[c] = 0.0;
   if (G.diss) {
-    const long pc = ((long)(i2 + G.g[2]) * G.P[1] + (i1 + G.g[1])) * G.P[0] + (i0 + G.g[0]);
-    const long pr = pc + sK;
+    const unsigned pc = 8u * (unsigned)(((i2 + G.g[2]) * G.P[1] + (i1 + G.g[1])) * G.P[0] + (i0 + G.g[0]));
+    const unsigned pr = pc + 8u * (unsigned)sK;
     // (the divisions of the averaged state are grouped so that each group shares one)
-    double rl = nd[F::RHO * G.PN + pc], rr = nd[F::RHO * G.PN + pr];
-    double pl = nd[F::P * G.PN + pc], pq = nd[F::P * G.PN + pr];
+    double rl = ndf(G, nd, F::RHO, pc), rr = ndf(G, nd, F::RHO, pr);
+    double pl = ndf(G, nd, F::P, pc), pq = ndf(G, nd, F::P, pr);
     // rho/p at the two nodes and its logarithm
     const double rpp = rcp_nr(pl * pq);
     double zl = rl * (pq * rpp), zr = rr * (pl * rpp);
     const double dR = logmean_den(rl, rr), dZ = logmean_den(zl, zr), rRZ = rcp_nr(dR * dZ);
-    double ilr = inv_logmean_r(rl, rr, nd[F::LNR * G.PN + pc], nd[F::LNR * G.PN + pr], rRZ * dZ);
-    double ilz = inv_logmean_r(zl, zr, nd[F::LNR * G.PN + pc] - nd[F::LNP * G.PN + pc],
-                               nd[F::LNR * G.PN + pr] - nd[F::LNP * G.PN + pr], rRZ * dR);
+    const double lrl = ndf(G, nd, F::LNR, pc), lrr = ndf(G, nd, F::LNR, pr);
+    double il2[2];
+    inv_logmean_rn<2>(G.lmc, {rl, zl}, {rr, zr}, {lrl, lrl - ndf(G, nd, F::LNP, pc)}, {lrr, lrr - ndf(G, nd, F::LNP, pr)},
+                      {rRZ * dZ, rRZ * dR}, il2);
+    const double ilr = il2[0], ilz = il2[1];
     double vb[D];
 #pragma unroll
-    for (int m = 0; m < D; ++m) vb[m] = 0.5 * (nd[(long)(F::V + m) * G.PN + pc] + nd[(long)(F::V + m) * G.PN + pr]);
+    for (int m = 0; m < D; ++m) vb[m] = 0.5 * (ndf(G, nd, F::V + m, pc) + ndf(G, nd, F::V + m, pr));
     double mm[D], L2 = 0.0;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      mm[j] = 0.5 * (nd[(long)(F::MS + K * D + j) * G.PN + pc] + nd[(long)(F::MS + K * D + j) * G.PN + pr]);
+      mm[j] = 0.5 * (ndf(G, nd, F::MS + K * D + j, pc) + ndf(G, nd, F::MS + K * D + j, pr));
       L2 += mm[j] * mm[j];
     }
-    double mtb = 0.5 * (nd[(long)(F::XS + K) * G.PN + pc] + nd[(long)(F::XS + K) * G.PN + pr]);
-    double L = sqrt(L2);
+    double mtb = 0.5 * (ndf(G, nd, F::XS + K, pc) + ndf(G, nd, F::XS + K, pr));
+    double L = sqrt_nr(L2);
     // L(rho) = 1/ilr and 1/L share a division
     const double rLL = rcp_nr(ilr * L);
     double rb = rLL * L;       // L(rho)
@@ -455,13 +539,13 @@ __device__ __forceinline__ bool flux_tile_eval(const Geo &G, const double *__res
     }
     double Eb = rb * (G.cv * Tb - G.a * rb) + 0.5 * rb * vv;
     E.H = (Eb + pb) * ilr;
-    E.c = sqrt(c2);
+    E.c = sqrt_nr(c2);
     E.c2G = c2 * G.cv * ob * G.iR;  // c^2 / Gamma with Gamma = R/(c_v (1 - b rho))
     double S0 = 0.5 * rb * Tb * ic2, S1 = G.R * G.R * rb * Tb * Tb * ic2 * (iac * G.delta * G.iR), St = rb * Tb;
     if (!(S0 > 0.0) || !(S1 > 0.0)) bad = 1u;
-    E.s0 = sqrt(fabs(S0));
-    E.s1 = sqrt(fabs(S1));
-    E.st = sqrt(fabs(St));
+    E.st = sqrt_nr(fabs(St));
+    E.s0 = E.st * (E.c * ic2) * 0.70710678118654752;  // sqrt(S0) = sqrt(St / 2) / c
+    E.s1 = sqrt_nr(fabs(S1));
     double Lam = fmax(fabs(mtb + L * (un - E.c)), fmax(fabs(mtb + L * un), fabs(mtb + L * (un + E.c))));
     double W[6][NV];
     double As[NV];  // rounding scale of W at the two nodes of the interface
@@ -490,14 +574,17 @@ __device__ __forceinline__ bool flux_tile_eval(const Geo &G, const double *__res
     double y[NV];
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
-      // [W]^WENO = wp - wm = (np dm - nm dp) / (dp dm), dp, dm > 0: one division per component
+      // wm = W2 + nm/dm, wp = W3 + np/dp, so [W]^WENO = wp - wm = jn / (dp dm) with
+      // jn = (W3 - W2) dp dm + np dm - nm dp, dp, dm > 0: one division per component
       double nm, dm, np, dp;
-      mrweno5_frac(G, W[0][c], W[1][c], W[2][c], W[3][c], W[4][c], nm, dm);
-      mrweno5_frac(G, W[5][c], W[4][c], W[3][c], W[2][c], W[1][c], np, dp);
-      double jn = np * dm - nm * dp, j0 = W[3][c] - W[2][c];
+      mrweno5_cfrac(G, W[0][c], W[1][c], W[2][c], W[3][c], W[4][c], nm, dm);
+      mrweno5_cfrac(G, W[5][c], W[4][c], W[3][c], W[2][c], W[1][c], np, dp);
+      double j0 = W[3][c] - W[2][c];
+      const double pd = dp * dm;
+      const double jn = fma(j0, pd, np * dm - nm * dp);
       // a plain jump below the rounding scale of W (2^-40 of its terms) counts as zero
       if (fabs(j0) <= ldexp(As[c], -40)) j0 = 0.0;
-      y[c] = ((jn > 0.0 && j0 > 0.0) || (jn < 0.0 && j0 < 0.0)) ? jn * rcp_nr(dp * dm) : 0.0;
+      y[c] = ((jn > 0.0 && j0 > 0.0) || (jn < 0.0 && j0 < 0.0)) ? jn * rcp_nr(pd) : 0.0;
     }
     // R y in the rotated frame, then rotate the momentum back (T^T)
     double b0 = E.s0 * y[0], b1 = E.s1 * y[1], b2 = E.s0 * y[D + 1];
@@ -532,13 +619,13 @@ __device__ __forceinline__ bool flux_tile_eval(const Geo &G, const double *__res
 }
 
 // flux_tile_eval, the fluxes written to Fo (component-major, nif interfaces per component)
-template <int D, int K, int TX, int TY, int TZ>
+template <int D, int K, int TX, int TY, int TZ, int PX = TX, int PY = TY>
 __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict__ nd, double *__restrict__ Fo,
                                           long nif, unsigned *flags, int bx0, int by0, int bz0,
                                           double *__restrict__ sP) {
   double Fl[D + 3];
   int a0, a1, a2;
-  if (!flux_tile_eval<D, K, TX, TY, TZ>(G, nd, flags, bx0, by0, bz0, sP, Fl, a0, a1, a2)) return;
+  if (!flux_tile_eval<D, K, TX, TY, TZ, PX, PY>(G, nd, flags, bx0, by0, bz0, sP, Fl, a0, a1, a2)) return;
   const int e0 = G.n[0] + (K == 0), e1 = G.n[1] + (K == 1);
   const long ti = ((long)a2 * e1 + a1) * e0 + a0;
 #pragma unroll
