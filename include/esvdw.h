@@ -78,6 +78,18 @@ typedef struct esvdw_params {
   double mesh_tol;      /* tolerance of the Jacobi stop test (max node update) */
   int fixed_mu;         /* 1: exactly mu sweeps; 0: stop once the update is < mesh_tol */
   int walls;            /* ESVDW_WALL_LO / _HI bits (outflow directions only; 0: none) */
+  /* Backward-facing step (Example 5.5; 2D, both directions outflow, fixed_mu = 1): the nodes
+   * i0 < step[0], i1 < step[1] form a solid block whose two faces are reflecting walls; the
+   * fluid is the L-shaped rest, with at least 3 nodes beyond the block in each direction.  Seen
+   * along a direction, the 3 solid nodes next to a face stand for the mirror images of the
+   * fluid nodes across it; the solid nodes keep their state (those next to the step hold the
+   * images, for the monitor), the mesh holds the images of the fluid mesh there, and the fluid
+   * nodes of the three 3 x 3 blocks around the corner keep their uniform positions.
+   * step = {0, 0}: no step. */
+  int step[2];
+  int inflow;           /* 1: the lo face of direction 0 (outflow, not a wall; 2D) holds the fixed
+                           state inflow_prim in its ghost layers */
+  double inflow_prim[4]; /* rho, v_1, v_2, p of the inflow state (admissible) */
 } esvdw_params;
 
 typedef struct esvdw_ctx esvdw_ctx;
@@ -158,7 +170,8 @@ int mesh_jacobi(esvdw_ctx *ctx, const double *omega, double *x, int nsweep, doub
  * outflow wall its mirror image is itself: normal coordinate 2 wall - x, tangential x) and moves
  * to x + relax (v - x).  nsweep sweeps on x (dim fields) with fixed omega; *resid_dev = the
  * largest |v - x| of the last sweep (may be NULL).  ESVDW_EINVAL unless 0 < relax < 2 and every
- * periodic direction has an even node count (the wrap must join opposite colours). */
+ * periodic direction has an even node count (the wrap must join opposite colours), and for a
+ * problem with the backward-facing step (not supported). */
 int mesh_sor(esvdw_ctx *ctx, const double *omega, double *x, int nsweep, double relax, double *resid_dev,
              hipStream_t stream);
 int mesh_limiter(esvdw_ctx *ctx, const double *x_n, const double *x_mu, double *gamma_dev, hipStream_t stream);

@@ -51,6 +51,7 @@ class Cfg(ctypes.Structure):
         ("monitor_kind", ctypes.c_int), ("kappa", ctypes.c_int), ("mon_var", ctypes.c_int * 2),
         ("alpha", ctypes.c_double * 3), ("n_filter", ctypes.c_int), ("mu", ctypes.c_int),
         ("mesh_tol", ctypes.c_double), ("fixed_mu", ctypes.c_int), ("walls", ctypes.c_int),
+        ("step", ctypes.c_int * 2), ("inflow", ctypes.c_int), ("inflow_prim", ctypes.c_double * 4),
     ]
 
 
@@ -88,6 +89,22 @@ def make_cfg(p):
             raise ValueError("walls are faces of outflow directions")
         walls |= 1 << (2 * int(k) + (1 if side == "hi" else 0))
     c.walls = walls
+    step = p.get("step")
+    if step:
+        if d != 2 or any(BC[p["bc"][k]] != BC["outflow"] for k in range(2)):
+            raise ValueError("the step needs a 2D problem with outflow-type directions")
+        if not (0 < step[0] and 0 < step[1] and step[0] + 3 <= c.n[0] and step[1] + 3 <= c.n[1]):
+            raise ValueError("the step needs 3 fluid nodes beyond it in each direction")
+        if not int(p["fixed_mu"]):
+            raise ValueError("the step takes the fixed sweep count of the mesh iteration")
+        c.step[0], c.step[1] = int(step[0]), int(step[1])
+    inflow = p.get("inflow")
+    if inflow is not None:
+        if d != 2 or BC[p["bc"][0]] != BC["outflow"] or (walls & 1):
+            raise ValueError("the inflow face is the lo face of an outflow direction 0 (2D)")
+        c.inflow = 1
+        for i in range(4):
+            c.inflow_prim[i] = float(inflow[i])
     return c
 
 
@@ -137,6 +154,9 @@ def lib(omp=False):
             "orc_step": (ctypes.c_double, [_CP, _D, _D, _D, ctypes.c_int]),
             "orc_init_state": (None, [_CP, _D, _D, _D]),
             "orc_total_entropy": (ctypes.c_double, [_CP, _D, _D]),
+            "orc_step_fill_state": (None, [_CP, _D, _D]),
+            "orc_step_fill_scalar": (None, [_CP, _D]),
+            "orc_step_fill_mesh": (None, [_CP, _D]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -250,6 +270,17 @@ class Oracle:
         xit = np.zeros((self.d,) + self.shape)
         self.L.orc_metrics(self._cp(), _p(_arr(x)), _p(None if xdot is None else _arr(xdot)), _p(met), _p(xit))
         return met, xit
+
+    def step_fill_state(self, JU, J):
+        """Images of the state at the solid nodes next to the step (in place)."""
+        self.L.orc_step_fill_state(self._cp(), _p(JU), _p(J))
+
+    def step_fill_scalar(self, w):
+        self.L.orc_step_fill_scalar(self._cp(), _p(w))
+
+    def step_fill_mesh(self, x):
+        """Images of the mesh at the solid nodes, uniform positions at the held nodes (in place)."""
+        self.L.orc_step_fill_mesh(self._cp(), _p(x))
 
     def init_state(self, prim, J):
         JU = np.zeros((self.nv,) + self.shape)

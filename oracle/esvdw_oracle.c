@@ -59,6 +59,11 @@ typedef struct {
   double mesh_tol;
   int fixed_mu;             /* 1: exactly mu sweeps; 0: stop when the update < tol */
   int walls;                /* bit 2k: the lo face of direction k is a reflecting wall; 2k+1: hi */
+  /* 2D backward-facing step (Example 5.5): the nodes i0 < step[0], i1 < step[1] are solid, the
+     fluid is the L-shaped rest; both faces of the step are reflecting walls.  0: no step. */
+  int step[2];
+  int inflow;               /* 1: the lo face of direction 0 holds the fixed state inflow_prim */
+  double inflow_prim[4];    /* rho, v_1, v_2, p */
 } orc_cfg;
 
 static unsigned g_flags = 0;
@@ -506,6 +511,105 @@ static long iidx(const orc_cfg *c, int i0, int i1, int i2) {
 
 static double dxi(const orc_cfg *c, int k) { return (c->hi[k] - c->lo[k]) / c->n[k]; }
 
+/* ------------------------------------------------------------------------- */
+/* Backward-facing step (Example 5.5; its geometry is a reading, see orc_cfg)  */
+/* ------------------------------------------------------------------------- */
+
+static int has_step(const orc_cfg *c) { return c->dim == 2 && c->step[0] > 0 && c->step[1] > 0; }
+
+/* node (i0, i1) lies in the solid block (indices may lie outside the grid) */
+static int solid(const orc_cfg *c, int i0, int i1) {
+  return has_step(c) && i0 < c->step[0] && i1 < c->step[1];
+}
+
+/* Seen along direction k, a solid node within 3 nodes of the step's face normal to k is the
+ * mirror image of a fluid node across that face (as a ghost node beyond a wall face of the
+ * domain is): returns 1 and the source's index along k in *src, else 0.  Along a line the
+ * fluid nodes form a suffix, so the images are the 3 solid nodes next to the first fluid one. */
+static int step_image(const orc_cfg *c, int k, int i0, int i1, int *src) {
+  if (!solid(c, i0, i1)) return 0;
+  if (k == 0 && i0 >= c->step[0] - 3) {
+    *src = 2 * c->step[0] - 1 - i0;
+    return 1;
+  }
+  if (k == 1 && i1 >= c->step[1] - 3) {
+    *src = 2 * c->step[1] - 1 - i1;
+    return 1;
+  }
+  return 0;
+}
+
+/* The step's corner couples the images of the two faces: the solid corner block is the image
+ * of the fluid block below-right of it across the vertical face and of the fluid block
+ * above-left of it across the horizontal one, and the metric stencils of the images near the
+ * corner reach those blocks and the fluid block diagonally above-right.  All of these agree
+ * when the three 3 x 3 fluid blocks around the corner hold their uniform positions (the mesh
+ * iteration does not move them) and the corner block holds its uniform positions too. */
+static int step_held(const orc_cfg *c, int i0, int i1) {
+  if (!has_step(c)) return 0;
+  int s0 = c->step[0], s1 = c->step[1];
+  int near0 = i0 >= s0 - 3 && i0 < s0 + 3, near1 = i1 >= s1 - 3 && i1 < s1 + 3;
+  return near0 && near1 && !solid(c, i0, i1);
+}
+
+/* State at the solid nodes within 3 of a face of the step: the image across that face of its
+ * fluid source (normal momentum reversed, J copied); the corner block, within 3 of both
+ * faces, takes the image across the vertical face (i0 = step[0]).  These values feed the
+ * monitor and keep the solid nodes admissible; the fluxes form the images along each direction
+ * themselves (rhs_padded).  Other solid nodes keep their values. */
+void orc_step_fill_state(const orc_cfg *c, double *JU, double *J) {
+  if (!has_step(c)) return;
+  long N = nodes(c);
+  for (int k = 1; k >= 0; --k)
+    for (int i1 = 0; i1 < c->step[1]; ++i1)
+      for (int i0 = 0; i0 < c->step[0]; ++i0) {
+        int src;
+        if (!step_image(c, k, i0, i1, &src)) continue;
+        long q = iidx(c, i0, i1, 0), qs = iidx(c, k == 0 ? src : i0, k == 1 ? src : i1, 0);
+        for (int v = 0; v < 4; ++v) JU[v * N + q] = (v == 1 + k ? -JU[v * N + qs] : JU[v * N + qs]);
+        J[q] = J[qs];
+      }
+}
+
+/* a scalar node field (the monitor) at the same solid nodes: the value of the source */
+void orc_step_fill_scalar(const orc_cfg *c, double *w) {
+  if (!has_step(c)) return;
+  for (int k = 1; k >= 0; --k)
+    for (int i1 = 0; i1 < c->step[1]; ++i1)
+      for (int i0 = 0; i0 < c->step[0]; ++i0) {
+        int src;
+        if (!step_image(c, k, i0, i1, &src)) continue;
+        w[iidx(c, i0, i1, 0)] = w[iidx(c, k == 0 ? src : i0, k == 1 ? src : i1, 0)];
+      }
+}
+
+/* Mesh at the solid nodes and the held fluid nodes, so that the stencils of the fluid nodes
+ * (metrics, monitor, Jacobi sweeps) see the image of the mesh across each face: a solid node
+ * within 3 of one face only holds the image of its source (normal coordinate 2 face - x, the
+ * other unchanged); the corner block, the held fluid nodes (step_held) and the other solid
+ * nodes hold their uniform positions. */
+void orc_step_fill_mesh(const orc_cfg *c, double *x) {
+  if (!has_step(c)) return;
+  long N = nodes(c);
+  int s0 = c->step[0], s1 = c->step[1];
+  double face[2] = {c->lo[0] + s0 * dxi(c, 0), c->lo[1] + s1 * dxi(c, 1)};
+  for (int i1 = 0; i1 < s1 + 3; ++i1)
+    for (int i0 = 0; i0 < s0 + 3; ++i0) {
+      long q = iidx(c, i0, i1, 0);
+      if (!solid(c, i0, i1) && !step_held(c, i0, i1)) continue;
+      int s, row = step_image(c, 0, i0, i1, &s), col = step_image(c, 1, i0, i1, &s);
+      if (!solid(c, i0, i1) || row == col) { /* held, corner block or deep inside: uniform */
+        x[q] = c->lo[0] + (i0 + 0.5) * dxi(c, 0);
+        x[N + q] = c->lo[1] + (i1 + 0.5) * dxi(c, 1);
+        continue;
+      }
+      int k = row ? 0 : 1, src;
+      step_image(c, k, i0, i1, &src);
+      long qs = iidx(c, k == 0 ? src : i0, k == 1 ? src : i1, 0);
+      for (int j = 0; j < 2; ++j) x[j * N + q] = j == k ? 2.0 * face[k] - x[j * N + qs] : x[j * N + qs];
+    }
+}
+
 /* Fill the ghost layers of nf padded scalar fields, direction by direction.
  * kind 0: state field (periodic wrap, outflow: nearest interior node; reflecting wall face:
  *         mirror image, sign reversed when the field is the momentum component `coord` == k;
@@ -731,6 +835,7 @@ void orc_uniform_mesh(const orc_cfg *c, double *x) {
         int ii[3] = {i0, i1, i2};
         for (int j = 0; j < d; ++j) x[j * N + iidx(c, i0, i1, i2)] = c->lo[j] + (ii[j] + 0.5) * dxi(c, j);
       }
+  orc_step_fill_mesh(c, x);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -821,8 +926,13 @@ static void interface_flux(const orc_cfg *c, double st[6][NVMAX], double mx[6][3
     }
   }
   /* jumps: plain [W] and reconstructed [W]^WENO = W+ - W-; sign matrix Y.  A plain jump
-     below the rounding level of the terms that form W (2^-40 of their magnitude) is taken
-     as zero, so Y = 0 there: Y only gates dissipation, so the flux stays entropy stable. */
+     below the rounding level of the vector W (2^-40 of the magnitude of all the terms that form
+     the W components at the two nodes) is taken as zero, so Y = 0 there: Y only gates
+     dissipation, so the flux stays entropy stable.  (A component's own terms can all be
+     rounding residue of exact zeros, e.g. a tangential velocity that vanishes by symmetry; its
+     plain jump is then noise whose sign must not decide Y.) */
+  double wscale = 0.0;
+  for (int r = 0; r < nv; ++r) wscale += Wmag[2][r] + Wmag[3][r];
   double YdW[NVMAX];
   for (int r = 0; r < nv; ++r) {
     double Wm = orc_mrweno5(c, W[0][r], W[1][r], W[2][r], W[3][r], W[4][r]);
@@ -832,9 +942,9 @@ static void interface_flux(const orc_cfg *c, double st[6][NVMAX], double mx[6][3
     if (diag) {
       diag[NVMAX + r] = jw;
       diag[2 * NVMAX + r] = j0;
-      diag[3 * NVMAX + r] = Wmag[2][r] + Wmag[3][r];
+      diag[3 * NVMAX + r] = wscale;
     }
-    if (fabs(j0) <= ldexp(Wmag[2][r] + Wmag[3][r], -40)) j0 = 0.0;
+    if (fabs(j0) <= ldexp(wscale, -40)) j0 = 0.0;
     int same = (jw > 0.0 && j0 > 0.0) || (jw < 0.0 && j0 < 0.0);
     YdW[r] = same ? jw : 0.0;
     if (diag) diag[r] = same ? 1.0 : 0.0;
@@ -887,14 +997,22 @@ static void rhs_padded(const orc_cfg *c, const pad_t *pm, double *const *Up, con
           il[ka] = ia;
           il[kb] = ib;
           const int i0 = il[0], i1 = il[1], i2 = il[2];
+          /* with a step, only the faces with a fluid node on their right (the first fluid node
+             of a line and beyond) carry a flux */
+          if (has_step(c) && solid(c, i0 + (k == 0), i1 + (k == 1))) continue;
           double st[6][NVMAX], mx[6][3], mt[6];
           for (int s = 0; s < 6; ++s) {
             int ii[3] = {i0, i1, i2};
             ii[k] += s - 2;
+            /* a solid node next to a face of the step: the mirror image of its fluid source
+               across that face (normal momentum, J xi_k/x_j for j != k and J xi_k/t reversed) */
+            int src, img = step_image(c, k, ii[0], ii[1], &src);
+            if (img) ii[k] = src;
             long qp = pidx(pm, ii[0], ii[1], ii[2]);
-            for (int v = 0; v < nv; ++v) st[s][v] = Up[v][qp];
-            for (int j = 0; j < d; ++j) mx[s][j] = metp[(k * d + j) * pm->N + qp];
-            mt[s] = xitp[k * pm->N + qp];
+            for (int v = 0; v < nv; ++v) st[s][v] = (img && v == 1 + k) ? -Up[v][qp] : Up[v][qp];
+            for (int j = 0; j < d; ++j)
+              mx[s][j] = (img && j != k) ? -metp[(k * d + j) * pm->N + qp] : metp[(k * d + j) * pm->N + qp];
+            mt[s] = img ? -xitp[k * pm->N + qp] : xitp[k * pm->N + qp];
           }
           double Fes[NVMAX], gt, prod, dg[4 * NVMAX];
           interface_flux(c, st, mx, mt, Fes, &gt, &prod, rec ? dg : NULL);
@@ -928,6 +1046,14 @@ static void rhs_padded(const orc_cfg *c, const pad_t *pm, double *const *Up, con
         }
     roff += (long)NR * nif;
   }
+  /* the solid nodes do not evolve */
+  if (has_step(c))
+    for (int i1 = 0; i1 < c->step[1]; ++i1)
+      for (int i0 = 0; i0 < c->step[0]; ++i0) {
+        long qi = iidx(c, i0, i1, 0);
+        for (int v = 0; v < nv; ++v) dJU[v * N + qi] = 0.0;
+        dJ[qi] = 0.0;
+      }
   if (prodsum) *prodsum = psum;
 }
 
@@ -945,6 +1071,16 @@ static double **pad_state(const orc_cfg *c, const pad_t *pm, const double *JU, c
           Up[v][pidx(pm, i0, i1, i2)] = JU[v * N + qi] / J[qi];
         }
     fill_ghosts(c, pm, Up[v], 0, v >= 1 && v <= d ? v - 1 : -1);
+  }
+  if (c->inflow) {
+    /* the lo face of direction 0 holds the fixed inflow state in all its ghost layers */
+    double pr[NVMAX], Uin[NVMAX];
+    for (int v = 0; v < nv; ++v) pr[v] = c->inflow_prim[v];
+    orc_prim_to_cons(c, pr, Uin);
+    for (int i2 = -pm->g[2]; i2 < pm->n[2] + pm->g[2]; ++i2)
+      for (int i1 = -pm->g[1]; i1 < pm->n[1] + pm->g[1]; ++i1)
+        for (int i0 = -pm->g[0]; i0 < 0; ++i0)
+          for (int v = 0; v < nv; ++v) Up[v][pidx(pm, i0, i1, i2)] = Uin[v];
   }
   return Up;
 }
@@ -1118,6 +1254,16 @@ void orc_rk_stage(const orc_cfg *c, int s, double dt, const double *JU0, const d
     double y = Js[q] + dt * LJ[q];
     Jout[q] = s == 0 ? y : a0 * J0[q] + a1 * y;
   }
+  if (has_step(c)) {
+    /* solid nodes keep the step's base values; those next to the step then take their images */
+    for (int i1 = 0; i1 < c->step[1]; ++i1)
+      for (int i0 = 0; i0 < c->step[0]; ++i0) {
+        long q = iidx(c, i0, i1, 0);
+        for (int v = 0; v < nv; ++v) JUout[v * N + q] = JU0[v * N + q];
+        Jout[q] = J0[q];
+      }
+    orc_step_fill_state(c, JUout, Jout);
+  }
   free(xs);
   free(LU);
   free(LJ);
@@ -1135,6 +1281,7 @@ double orc_cfl_dt(const orc_cfg *c, const double *JU, const double *J, const dou
   orc_metrics(c, x, NULL, met, NULL);
   double mx = 0.0;
   for (long q = 0; q < N; ++q) {
+    if (has_step(c) && solid(c, (int)(q % c->n[0]), (int)(q / c->n[0]))) continue; /* fluid nodes only */
     double U[NVMAX], z[NVMAX];
     for (int v = 0; v < nv; ++v) U[v] = JU[v * N + q] / J[q];
     cons_to_z(c, U, z);
@@ -1211,7 +1358,7 @@ void orc_monitor(const orc_cfg *c, const double *JU, const double *J, double *om
           }
           double val = c->monitor_kind == MON_VDW ? s2 : sqrt(s2);
           term[t * N + qi] = val;
-          if (val > mxv[t]) mxv[t] = val;
+          if (val > mxv[t] && !solid(c, i0, i1)) mxv[t] = val; /* maxima over the fluid nodes */
         }
       }
   for (long q = 0; q < N; ++q) {
@@ -1220,6 +1367,7 @@ void orc_monitor(const orc_cfg *c, const double *JU, const double *J, double *om
       if (mxv[t] > 0.0) s += c->alpha[t] * term[t * N + q] / mxv[t];
     omega[q] = sqrt(s);
   }
+  orc_step_fill_scalar(c, omega);
   free(term);
   free(rho);
   free(G);
@@ -1250,6 +1398,7 @@ void orc_filter(const orc_cfg *c, double *omega, int npass) {
               }
           omega[iidx(c, i0, i1, i2)] = s;
         }
+    orc_step_fill_scalar(c, omega);
   }
   (void)N;
   free(w);
@@ -1290,15 +1439,17 @@ int orc_jacobi(const orc_cfg *c, const double *omega, double *x, int nsweep, dou
             den += (wp + wm) / h2;
             for (int j = 0; j < d; ++j) num[j] += (wp * xp[j][qpp] + wm * xp[j][qpm]) / h2;
           }
+          const int held = solid(c, i0, i1) || step_held(c, i0, i1); /* set by the fill below */
           for (int j = 0; j < d; ++j) {
             double v = num[j] / den;
             double u = fabs(v - x[j * N + qi]);
-            if (u > res) res = u;
+            if (u > res && !held) res = u;
             xnew[j * N + qi] = v;
           }
         }
     free_fields(xp, d);
     memcpy(x, xnew, sizeof(double) * d * N);
+    orc_step_fill_mesh(c, x);
     ++it;
     if (tol > 0.0 && res < tol) break;
   }
@@ -1324,6 +1475,7 @@ int orc_sor(const orc_cfg *c, const double *omega, double *x, int nsweep, double
   long N = nodes(c);
   for (int k = 0; k < d; ++k)
     if (c->bc[k] == BC_PERIODIC && c->n[k] % 2) return -1;
+  if (has_step(c)) return -1;
   pad_t p1 = make_pad(c, 1);
   double *w = calloc(p1.N, sizeof(double));
   to_pad(c, &p1, omega, w);
@@ -1387,6 +1539,7 @@ double orc_limiter(const orc_cfg *c, const double *xn, const double *xmu) {
     for (int i1 = 0; i1 < p1.n[1]; ++i1)
       for (int i0 = 0; i0 < p1.n[0]; ++i0) {
         long qi = iidx(c, i0, i1, i2), qp = pidx(&p1, i0, i1, i2);
+        if (solid(c, i0, i1)) continue; /* fluid nodes only */
         for (int k = 0; k < d; ++k) {
           double dx = xmu[k * N + qi] - xn[k * N + qi];
           int ip[3] = {i0, i1, i2}, im[3] = {i0, i1, i2};
@@ -1452,8 +1605,10 @@ double orc_step(const orc_cfg *c, double *JU, double *J, double *x, int moving) 
   orc_rk_stage(c, 0, dt, JU, J, JU, J, x, xd, JU1, J1);
   orc_rk_stage(c, 1, dt, JU, J, JU1, J1, x, xd, JU2, J2);
   orc_rk_stage(c, 2, dt, JU, J, JU2, J2, x, xd, JU, J);
-  if (moving)
+  if (moving) {
     for (long q = 0; q < d * N; ++q) x[q] += dt * xdot[q];
+    orc_step_fill_mesh(c, x);
+  }
   free(JU1);
   free(J1);
   free(JU2);

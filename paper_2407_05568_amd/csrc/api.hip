@@ -30,6 +30,17 @@ int params_valid(const esvdw_params *p) {
     pn *= (double)pk;
   }
   if (pn * 8.0 >= 4294967296.0) return 0;
+  if (p->step[0] != 0 || p->step[1] != 0) {
+    if (p->dim != 2 || p->bc[0] != ESVDW_BC_OUTFLOW || p->bc[1] != ESVDW_BC_OUTFLOW || !p->fixed_mu) return 0;
+    if (p->step[0] < 1 || p->step[1] < 1 || p->step[0] + 3 > p->n[0] || p->step[1] + 3 > p->n[1]) return 0;
+  }
+  if (p->inflow) {
+    if (p->dim != 2 || p->bc[0] != ESVDW_BC_OUTFLOW || (p->walls & ESVDW_WALL_LO(0))) return 0;
+    const double rho = p->inflow_prim[0], ob = 1.0 - p->b * rho;
+    if (!(rho > 0.0) || !(ob > 0.0)) return 0;
+    const double T = (p->inflow_prim[3] + p->a * rho * rho) * ob / (rho * p->R);
+    if (!(p->R * T - 2.0 * p->a * rho * ob * ob > 0.0)) return 0;
+  }
   return 1;
 }
 
@@ -64,6 +75,18 @@ void make_geo(const esvdw_params *p, Geo *G) {
   G->b = p->b;
   G->delta = p->R / p->cv;
   G->iR = 1.0 / p->R;
+  if (p->step[0] > 0 && p->step[1] > 0) {
+    G->s0 = p->step[0];
+    G->s1 = p->step[1];
+  }
+  if (p->inflow) {
+    const double rho = p->inflow_prim[0];
+    G->inflow = 1;
+    G->qin[0] = rho;
+    G->qin[1] = p->inflow_prim[1];
+    G->qin[2] = p->inflow_prim[2];
+    G->qin[3] = (p->inflow_prim[3] + p->a * rho * rho) * (1.0 - p->b * rho) / (rho * p->R);
+  }
   for (int k = 0; k < 7; ++k) G->lmc[k] = 1.0 / (15 - 2 * k);
   G->lmc[7] = 1.0 / 17;
   G->wl0 = p->weno_lin[0];
@@ -201,7 +224,8 @@ int rk_stage(esvdw_ctx *c, int s, const double *dt_dev, const double *JU0, const
   if (launch_rhs(c, JUs, Js, nullptr, nullptr, xs, xdot, 0.0, 1, s, dt_dev, JU0, J0, JUout, Jout, st))
     return ESVDW_EHIP;
   if (s == 2 && x_next && xdot)
-    if (launch_axpy_mesh(c, x_n, xdot, dt_dev, 1.0, x_next, st)) return ESVDW_EHIP;
+    if (launch_axpy_mesh(c, x_n, xdot, dt_dev, 1.0, x_next, st) || launch_step_fill_mesh(c->G, x_next, st))
+      return ESVDW_EHIP;
   return ESVDW_OK;
 }
 
@@ -217,7 +241,7 @@ int mesh_jacobi(esvdw_ctx *c, const double *omega, double *x, int nsweep, double
 
 int mesh_sor(esvdw_ctx *c, const double *omega, double *x, int nsweep, double relax, double *resid_dev,
              hipStream_t st) {
-  if (!c || !omega || !x || nsweep < 0 || !(relax > 0.0 && relax < 2.0)) return ESVDW_EINVAL;
+  if (!c || !omega || !x || nsweep < 0 || !(relax > 0.0 && relax < 2.0) || c->G.s0 > 0) return ESVDW_EINVAL;
   for (int k = 0; k < c->G.dim; ++k)
     if (c->G.bc[k] == ESVDW_BC_PERIODIC && c->G.n[k] % 2) return ESVDW_EINVAL;
   return launch_sor(c, omega, x, nsweep, relax, resid_dev, st) ? ESVDW_EHIP : ESVDW_OK;
@@ -313,7 +337,8 @@ int esvdw_step(esvdw_ctx *c, double *JU, double *J, double *x, int moving, doubl
   if (launch_rhs_mesh(c, JU, J, nullptr, nullptr, x, xd, 0.0, 1, 0, dt_dev, JU, J, aU, aJ, x, xd, 1.0, c->xtmp, st) ||
       launch_rhs_mesh(c, aU, aJ, nullptr, nullptr, c->xtmp, xd, 0.0, 1, 1, dt_dev, JU, J, bU, bJ, x, xd, 0.5, c->xtmp,
                       st) ||
-      launch_rhs_mesh(c, bU, bJ, nullptr, nullptr, c->xtmp, xd, 0.0, 1, 2, dt_dev, JU, J, JU, J, x, xd, 1.0, x, st))
+      launch_rhs_mesh(c, bU, bJ, nullptr, nullptr, c->xtmp, xd, 0.0, 1, 2, dt_dev, JU, J, JU, J, x, xd, 1.0, x, st) ||
+      launch_step_fill_mesh(c->G, x, st))
     return ESVDW_EHIP;
   return ESVDW_OK;
 }

@@ -515,7 +515,9 @@ int esvdw_batch_create(int ninst, const esvdw_params *params, esvdw_batch **out)
   *out = nullptr;
   if (ninst < 1 || !params) return ESVDW_EINVAL;
   for (int i = 0; i < ninst; ++i)
-    if (!params_valid(&params[i]) || params[i].dim != 2 || params[i].walls != 0) return ESVDW_EINVAL;
+    if (!params_valid(&params[i]) || params[i].dim != 2 || params[i].walls != 0 || params[i].step[0] != 0 ||
+        params[i].step[1] != 0 || params[i].inflow != 0)
+      return ESVDW_EINVAL;
   esvdw_batch *b = new esvdw_batch();
   b->ninst = ninst;
   (void)hipGetDevice(&b->dev);

@@ -26,6 +26,9 @@ struct Geo {
   double wl0, wl1, wl2, weps, iwl0;
   int diss;
   double lmc[8];  // log-mean series coefficients 1/15, 1/13, ..., 1/3, 1/17 (see inv_logmean_rn)
+  int s0, s1;     // 2D backward-facing step: nodes i0 < s0, i1 < s1 are solid (s0 = 0: none)
+  int inflow;     // 1: the lo face of direction 0 holds the fixed state qin
+  double qin[4];  // inflow rho, v_1, v_2, T
 };
 
 // sixth-order central / high-order flux coefficients alpha_{3,m}: sum m a = 1, sum m^3 a = sum m^5 a = 0
@@ -72,6 +75,29 @@ __device__ __forceinline__ int state_src(int i, int n, int bc, int walls, int k)
   if (bc == ESVDW_BC_PERIODIC) return i - floordiv(i, n) * n;
   if (i < 0) return (walls & ESVDW_WALL_LO(k)) ? -1 - i : 0;
   return (walls & ESVDW_WALL_HI(k)) ? 2 * n - 1 - i : n - 1;
+}
+
+// ---- the backward-facing step (2D): a solid block of nodes whose two faces are walls ----------
+__device__ __forceinline__ bool step_solid(const Geo &G, int i0, int i1) {
+  return G.s0 > 0 && i0 < G.s0 && i1 < G.s1;
+}
+// Seen along direction K, a solid node within 3 nodes of the step's face normal to K is the
+// mirror image of a fluid node across that face: true, with the source's index along K in src.
+__device__ __forceinline__ bool step_image(const Geo &G, int K, int i0, int i1, int &src) {
+  if (!step_solid(G, i0, i1)) return false;
+  if (K == 0 && i0 >= G.s0 - 3) {
+    src = 2 * G.s0 - 1 - i0;
+    return true;
+  }
+  if (K == 1 && i1 >= G.s1 - 3) {
+    src = 2 * G.s1 - 1 - i1;
+    return true;
+  }
+  return false;
+}
+// fluid nodes held at their uniform positions: the three 3 x 3 blocks around the step's corner
+__device__ __forceinline__ bool step_pinned(const Geo &G, int i0, int i1) {
+  return G.s0 > 0 && i0 >= G.s0 - 3 && i0 < G.s0 + 3 && i1 >= G.s1 - 3 && i1 < G.s1 + 3 && !step_solid(G, i0, i1);
 }
 
 __device__ __forceinline__ long lin(const Geo &G, int i0, int i1, int i2) {

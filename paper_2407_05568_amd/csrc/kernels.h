@@ -42,6 +42,10 @@ int launch_cfl_noalloc(const Geo &G, double cfl, double dt_fixed, const double *
 int launch_xdot(esvdw_ctx *c, const double *xn, const double *xmu, const double *gam, const double *dtp, double *xdot,
                 hipStream_t st);
 int launch_copy(const double *src, double *dst, long n, hipStream_t st);
+// backward-facing step: values at the solid nodes (no-ops without a step)
+int launch_step_fill_state(const Geo &G, double *JU, double *J, hipStream_t st);
+int launch_step_fill_scalar(const Geo &G, double *w, hipStream_t st);
+int launch_step_fill_mesh(const Geo &G, double *x, hipStream_t st);
 int launch_add(const double *a, const double *b, double *dst, long n, hipStream_t st);
 int launch_flux_only(esvdw_ctx *c, int K, hipStream_t st);
 int launch_grad_rho_terms(esvdw_ctx *c, const double *JU, const double *J, hipStream_t st);

@@ -46,6 +46,56 @@ __global__ void k_final(const double *__restrict__ part, long nb, double *dst, i
   if (threadIdx.x == 0) *dst = v;
 }
 
+// ---- the backward-facing step: values at the solid nodes ---------------------------------
+// A solid node within 3 of one face of the step holds the image of its fluid source across
+// that face; within 3 of both (the corner block) the image across the vertical face
+// (i0 = s0).  Scalars (the monitor) copy the source.  One thread per node of the solid block.
+__global__ void k_step_fill_scalar(Geo G, double *__restrict__ w) {
+  const int i0 = blockIdx.x * blockDim.x + threadIdx.x, i1 = blockIdx.y;
+  if (i0 >= G.s0 || i1 >= G.s1) return;
+  int src;
+  if (step_image(G, 0, i0, i1, src)) w[lin(G, i0, i1, 0)] = w[lin(G, src, i1, 0)];
+  else if (step_image(G, 1, i0, i1, src)) w[lin(G, i0, i1, 0)] = w[lin(G, i0, src, 0)];
+}
+
+// The mesh: a solid node within 3 of one face only holds the image of its fluid source (normal
+// coordinate 2 face - x, the other unchanged); the corner block, the other solid nodes and the
+// fluid nodes held at the corner (step_pinned) their uniform positions.  One thread per node of
+// the (s0 + 3) x (s1 + 3) rectangle; the sources read are fluid nodes not written here.
+__global__ void k_step_fill_mesh(Geo G, double *__restrict__ x) {
+  const int i0 = blockIdx.x * blockDim.x + threadIdx.x, i1 = blockIdx.y;
+  if (i0 >= G.s0 + 3 || i1 >= G.s1 + 3) return;
+  const bool sol = step_solid(G, i0, i1);
+  if (!sol && !step_pinned(G, i0, i1)) return;
+  const long t = lin(G, i0, i1, 0);
+  int s;
+  const bool row = step_image(G, 0, i0, i1, s), col = step_image(G, 1, i0, i1, s);
+  if (sol && row != col) {
+    const int k = row ? 0 : 1;
+    int src;
+    step_image(G, k, i0, i1, src);
+    const long ts = k == 0 ? lin(G, src, i1, 0) : lin(G, i0, src, 0);
+    const double face = G.lo[k] + (k == 0 ? G.s0 : G.s1) * G.dxi[k];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) x[(long)j * G.N + t] = j == k ? 2.0 * face - x[(long)j * G.N + ts] : x[(long)j * G.N + ts];
+  } else {
+    x[t] = G.lo[0] + (i0 + 0.5) * G.dxi[0];
+    x[G.N + t] = G.lo[1] + (i1 + 0.5) * G.dxi[1];
+  }
+}
+
+int launch_step_fill_scalar(const Geo &G, double *w, hipStream_t st) {
+  if (G.s0 <= 0) return 0;
+  hipLaunchKernelGGL(k_step_fill_scalar, dim3(nblk(G.s0, 64), G.s1), dim3(64), 0, st, G, w);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_step_fill_mesh(const Geo &G, double *x, hipStream_t st) {
+  if (G.s0 <= 0) return 0;
+  hipLaunchKernelGGL(k_step_fill_mesh, dim3(nblk(G.s0 + 3, 64), G.s1 + 3), dim3(64), 0, st, G, x);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 // ---- monitor -------------------------------------------------------------------
 template <int D>
 __global__ void k_rho_G(Geo G, const double *__restrict__ JU, const double *__restrict__ J, double *__restrict__ rg) {
@@ -61,7 +111,10 @@ __global__ void k_mon_terms(Geo G, int kind, int kappa, int var0, int var1, cons
   NODE_COORDS(G.n[0], G.n[1]);
   double val[3] = {0.0, 0.0, 0.0};
   int nterm = kind == ESVDW_MON_VDW ? kappa + 1 : 2;
-  if (inside) mon_terms_point<D>(G, kind, kappa, var0, var1, rg, term, i0, i1, i2, val);
+  if (inside) {
+    mon_terms_point<D>(G, kind, kappa, var0, var1, rg, term, i0, i1, i2, val);
+    if (step_solid(G, i0, i1)) val[0] = val[1] = val[2] = 0.0;  // maxima over the fluid nodes
+  }
   for (int q = 0; q < 3; ++q) {
     if (q >= nterm) break;
     double mq = block_max(val[q]);
@@ -365,7 +418,7 @@ __global__ void k_sor(Geo G, const double *__restrict__ omega, double *__restric
 template <int D>
 __global__ void k_limiter(Geo G, const double *__restrict__ xn, const double *__restrict__ xmu, double *part) {
   NODE_COORDS(G.n[0], G.n[1]);
-  const double g = inside ? limiter_point<D>(G, xn, xmu, i0, i1, i2) : 1.0;
+  const double g = (inside && !step_solid(G, i0, i1)) ? limiter_point<D>(G, xn, xmu, i0, i1, i2) : 1.0;
   double mg = block_min(g);
   if (flat_tid() == 0) part[flat_bid()] = mg;
 }
@@ -376,7 +429,7 @@ template <int D>
 __global__ void k_cfl(Geo G, const double *__restrict__ JU, const double *__restrict__ J,
                       const double *__restrict__ x, const double *__restrict__ met, double *part) {
   NODE_COORDS(G.n[0], G.n[1]);
-  double s = inside ? cfl_rate<D>(G, JU, J, x, met, i0, i1, i2) : 0.0;
+  double s = (inside && !step_solid(G, i0, i1)) ? cfl_rate<D>(G, JU, J, x, met, i0, i1, i2) : 0.0;
   double ms = block_max(s);
   if (flat_tid() == 0) part[flat_bid()] = ms;
 }
@@ -398,7 +451,7 @@ __global__ void __launch_bounds__(256) k_cfl_t2(Geo G, const double *__restrict_
   for (int r = 0; r < CF_TY / 4; ++r) {
     const int u = tx, v = ty + 4 * r;
     const int i0 = b0 + u, i1 = b1 + v;
-    if (i0 >= G.n[0] || i1 >= G.n[1]) continue;
+    if (i0 >= G.n[0] || i1 >= G.n[1] || step_solid(G, i0, i1)) continue;  // fluid nodes only
     double m[2][2];
     mesh_tile_metrics<CF_TX, CF_TY>(G, T, u, v, m);
     mx = fmax(mx, cfl_rate_m<2>(G, JU, J, (long)i1 * G.n[0] + i0, m));
@@ -514,11 +567,14 @@ template <int D> static int monitor_d(esvdw_ctx *c, const double *JU, const doub
   hipLaunchKernelGGL(k_final_many, dim3(nterm), dim3(1024), 0, st, c->part, c->npart, nb, c->scal + SC_MON);
   // 2D outflow grids run up to JT_H passes per launch; the filtered result must end in `omega`:
   // start in omega2 when the launch count is odd
-  const bool multi = D == 2 && G.bc[0] != ESVDW_BC_PERIODIC && G.bc[1] != ESVDW_BC_PERIODIC && p.n_filter >= 2;
+  // (with the step every pass is its own launch, followed by the images at the solid nodes)
+  const bool multi = D == 2 && G.bc[0] != ESVDW_BC_PERIODIC && G.bc[1] != ESVDW_BC_PERIODIC && p.n_filter >= 2 &&
+                     G.s0 == 0;
   const int nlaunch = multi ? (p.n_filter + JT_H - 1) / JT_H : p.n_filter;
   double *cur = (nlaunch % 2) ? c->omega2 : omega;
   double *oth = (nlaunch % 2) ? omega : c->omega2;
   hipLaunchKernelGGL(k_mon_omega, g, b, 0, st, G, nterm, p.alpha[0], p.alpha[1], p.alpha[2], c->mterm, c->scal, cur);
+  if (launch_step_fill_scalar(G, cur, st)) return -1;
   const dim3 gm((G.n[0] + JT_X - 1) / JT_X, (G.n[1] + JT_Y - 1) / JT_Y, 1);
   for (int done = 0; done < p.n_filter;) {
     const int k = multi ? (p.n_filter - done < JT_H ? p.n_filter - done : JT_H) : 1;
@@ -528,6 +584,7 @@ template <int D> static int monitor_d(esvdw_ctx *c, const double *JU, const doub
     cur = oth;
     oth = tmp;
     done += k;
+    if (launch_step_fill_scalar(G, cur, st)) return -1;
   }
   return CHK();
 }
@@ -551,7 +608,8 @@ static int jacobi_d(esvdw_ctx *c, const double *omega, const double *x0, double 
   // between x and the scratch, so x0 is never written
   const double *a0 = x0 ? x0 : x;
   double *a = x, *o = c->xtmp;
-  const bool multi = D == 2 && G.bc[0] != ESVDW_BC_PERIODIC && G.bc[1] != ESVDW_BC_PERIODIC && nsweep >= 2;
+  const bool multi = D == 2 && G.bc[0] != ESVDW_BC_PERIODIC && G.bc[1] != ESVDW_BC_PERIODIC && nsweep >= 2 &&
+                     G.s0 == 0;
   if (multi) {
     const dim3 gm((G.n[0] + JT_X - 1) / JT_X, (G.n[1] + JT_Y - 1) / JT_Y, 1);
     const long nbm = (long)gm.x * gm.y;  // <= 4 npart
@@ -571,6 +629,7 @@ static int jacobi_d(esvdw_ctx *c, const double *omega, const double *x0, double 
     bool last = it == nsweep - 1 && resid_dev;
     hipLaunchKernelGGL(k_jacobi<D>, g, b, 0, st, G, omega, it == 0 ? a0 : a, o, last ? c->part : nullptr);
     if (last) hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, c->part, nb, c->scal + SC_RESID, 0);
+    if (launch_step_fill_mesh(G, o, st)) return -1;  // the images and held nodes after each sweep
     double *tmp = a;
     a = o;
     o = tmp;

@@ -196,13 +196,14 @@ __global__ void __launch_bounds__(256) k_nodes_t2(Geo G, const double *__restric
 
 // =============================== interface fluxes ================================
 
-template <int D, int K>
+// ST: the 2D backward-facing step (solid nodes next to its faces stand for mirror images)
+template <int D, int K, bool ST = false>
 __global__ void __launch_bounds__(256, 3) k_flux(Geo G, const double *__restrict__ nd, double *__restrict__ Fo, long nif,
                                               unsigned *flags) {
   using TL = Tile<D, K>;
   __shared__ double sP[FluxLds<D, K, TL::X, TL::Y, TL::Z>::SIZE];
-  flux_tile<D, K, TL::X, TL::Y, TL::Z, TL::PX, TL::PY>(G, nd, Fo, nif, flags, blockIdx.x * TL::X, blockIdx.y * TL::Y,
-                                                       blockIdx.z * TL::Z, sP);
+  flux_tile<D, K, TL::X, TL::Y, TL::Z, TL::PX, TL::PY, ST>(G, nd, Fo, nif, flags, blockIdx.x * TL::X,
+                                                           blockIdx.y * TL::Y, blockIdx.z * TL::Z, sP);
 }
 
 // =============================== update ==========================================
@@ -216,6 +217,9 @@ __global__ void __launch_bounds__(256, 3) k_flux(Geo G, const double *__restrict
 #define FU_TX 62
 #define FU_PX 64
 #define FU_TY 4
+// ST: the 2D backward-facing step; its solid nodes keep the step's base values (mode 1) or get a
+// zero right-hand side (mode 0)
+template <bool ST>
 __global__ void __launch_bounds__(256, 3)
     k_flux_upd2(Geo G, const double *__restrict__ nd, const double *__restrict__ F1, long nif1, int mode, int s,
                 const double *__restrict__ dtp, const double *__restrict__ base_JU, const double *__restrict__ base_J,
@@ -227,7 +231,7 @@ __global__ void __launch_bounds__(256, 3)
   const int bx0 = blockIdx.x * (FU_TX - 1), by0 = blockIdx.y * FU_TY;
   double Fl[5];
   int a0, a1, a2;
-  const bool ok = flux_tile_eval<2, 0, FU_TX, FU_TY, 1, FU_PX>(G, nd, flags, bx0, by0, 0, sP, Fl, a0, a1, a2);
+  const bool ok = flux_tile_eval<2, 0, FU_TX, FU_TY, 1, FU_PX, FU_TY, ST>(G, nd, flags, bx0, by0, 0, sP, Fl, a0, a1, a2);
   __syncthreads();  // every thread has read its pair fluxes
   const int tid = threadIdx.x, tx = tid % FU_PX, ty = tid / FU_PX;
   if (ok) {
@@ -238,6 +242,16 @@ __global__ void __launch_bounds__(256, 3)
   const int i0 = bx0 + tx, i1 = by0 + ty;
   if (tx >= FU_TX - 1 || i0 >= G.n[0] || i1 >= G.n[1]) return;
   const long t = (long)i1 * G.n[0] + i0;
+  if (mout) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) mout[(long)j * G.N + t] = mx[(long)j * G.N + t] + mf * (*dtp) * mxd[(long)j * G.N + t];
+  }
+  if (ST && step_solid(G, i0, i1)) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) out_JU[(long)c * G.N + t] = mode == 1 ? base_JU[(long)c * G.N + t] : 0.0;
+    out_J[t] = mode == 1 ? base_J[t] : 0.0;
+    return;
+  }
   double L[5];
 #pragma unroll
   for (int c = 0; c < 5; ++c) L[c] = 0.0;
@@ -249,10 +263,28 @@ __global__ void __launch_bounds__(256, 3)
     for (int c = 0; c < 5; ++c) L[c] += (F1[(long)c * nif1 + r] - F1[(long)c * nif1 + r + G.n[0]]) * G.idxi[1];
   }
   update_combine<2>(G, L, t, mode, s, dtp, base_JU, base_J, in_JU, in_J, out_JU, out_J, flags);
-  if (mout) {
+}
+
+// backward-facing step: the state at the solid nodes next to the step becomes the image of its
+// fluid source (normal momentum reversed, J copied); the corner block takes the image across
+// the vertical face.  One thread per node of the solid block; sources are fluid nodes.
+__global__ void k_step_fill_state(Geo G, double *__restrict__ JU, double *__restrict__ J) {
+  const int i0 = blockIdx.x * blockDim.x + threadIdx.x, i1 = blockIdx.y;
+  if (i0 >= G.s0 || i1 >= G.s1) return;
+  int src, k;
+  if (step_image(G, 0, i0, i1, src)) k = 0;
+  else if (step_image(G, 1, i0, i1, src)) k = 1;
+  else return;
+  const long t = lin(G, i0, i1, 0), ts = k == 0 ? lin(G, src, i1, 0) : lin(G, i0, src, 0);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) mout[(long)j * G.N + t] = mx[(long)j * G.N + t] + mf * (*dtp) * mxd[(long)j * G.N + t];
-  }
+  for (int c = 0; c < 4; ++c) JU[(long)c * G.N + t] = (c == 1 + k ? -1.0 : 1.0) * JU[(long)c * G.N + ts];
+  J[t] = J[ts];
+}
+
+int launch_step_fill_state(const Geo &G, double *JU, double *J, hipStream_t st) {
+  if (G.s0 <= 0) return 0;
+  hipLaunchKernelGGL(k_step_fill_state, dim3((G.s0 + 63) / 64, G.s1), dim3(64), 0, st, G, JU, J);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 
@@ -340,6 +372,12 @@ template <int D, int K> static void launch_flux_dk(esvdw_ctx *c, hipStream_t st)
   const Geo &G = c->G;
   int e0 = G.n[0] + (K == 0), e1 = G.n[1] + (K == 1), e2 = G.n[2] + (K == 2);
   dim3 grid((e0 + TL::X - 1) / TL::X, (e1 + TL::Y - 1) / TL::Y, (e2 + TL::Z - 1) / TL::Z);
+  if constexpr (D == 2) {
+    if (G.s0 > 0) {
+      hipLaunchKernelGGL((k_flux<2, K, true>), grid, dim3(256), 0, st, G, c->node, c->flux[K], c->nif[K], c->flags);
+      return;
+    }
+  }
   hipLaunchKernelGGL((k_flux<D, K>), grid, dim3(256), 0, st, G, c->node, c->flux[K], c->nif[K], c->flags);
 }
 
@@ -373,8 +411,14 @@ static int rhs_pipeline_d(esvdw_ctx *c, const double *JU, const double *J, const
     // direction 1 first; the direction-0 flux kernel then also forms the update
     launch_flux_d<D>(c, 1, st);
     dim3 gf((G.n[0] + FU_TX - 2) / (FU_TX - 1), (G.n[1] + FU_TY - 1) / FU_TY, 1);
-    hipLaunchKernelGGL(k_flux_upd2, gf, dim3(256), 0, st, G, c->node, c->flux[1], c->nif[1], mode, s, dtp, bJU, bJ,
-                       JU, J, oJU, oJ, c->flags, mx, mxd, mf, mout);
+    if (G.s0 > 0) {
+      hipLaunchKernelGGL(k_flux_upd2<true>, gf, dim3(256), 0, st, G, c->node, c->flux[1], c->nif[1], mode, s, dtp,
+                         bJU, bJ, JU, J, oJU, oJ, c->flags, mx, mxd, mf, mout);
+      if (mode == 1 && launch_step_fill_state(G, oJU, oJ, st)) return -1;
+    } else {
+      hipLaunchKernelGGL(k_flux_upd2<false>, gf, dim3(256), 0, st, G, c->node, c->flux[1], c->nif[1], mode, s, dtp,
+                         bJU, bJ, JU, J, oJU, oJ, c->flags, mx, mxd, mf, mout);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
   }
   launch_flux_d<D>(c, 0, st);
@@ -408,6 +452,7 @@ int launch_uniform_mesh(esvdw_ctx *c, double *x, hipStream_t st) {
   dim3 g, b;
   node_grid(c->G.n[0], c->G.n[1], c->G.n[2], g, b);
   hipLaunchKernelGGL(k_uniform_mesh, g, b, 0, st, c->G, x);
+  if (launch_step_fill_mesh(c->G, x, st)) return -1;
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

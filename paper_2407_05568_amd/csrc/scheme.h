@@ -52,6 +52,17 @@ __device__ __forceinline__ void node_state(const Geo &G, const double *__restric
         v[q] = -v[q];
   }
   double e = JU[(long)(D + 1) * G.N + s] * iJ * irho - 0.5 * v2;
+  if (G.inflow && i0 < 0) {  // the inflow face's ghost layers hold the fixed inflow state
+    rho = G.qin[0];
+    irho = 1.0 / rho;
+    v2 = 0.0;
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+      v[m] = G.qin[1 + m];
+      v2 += v[m] * v[m];
+    }
+    e = G.cv * G.qin[3] - G.a * rho;
+  }
   double T = (e + G.a * rho) / G.cv;
   double iT = 1.0 / T;
   double ob = 1.0 - G.b * rho;
@@ -195,6 +206,17 @@ __device__ __forceinline__ void load_pq(const Geo &G, const double *__restrict__
   q.mt = ndf(G, nd, F::XS + K, ob);
 }
 
+// node data of the mirror image across a face normal to K: the velocity component and the
+// metrics J dxi_K/dx_j (j != K) and J dxi_K/dt change sign
+template <int D, int K>
+__device__ __forceinline__ void pq_mirror(Pq<D> &q) {
+  q.v[K] = -q.v[K];
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+    if (j != K) q.m[j] = -q.m[j];
+  q.mt = -q.mt;
+}
+
 // Two-point EC flux (eq. ECfluxMM with the closed-form U~, F~_j of Section 3.1), written in
 // contracted form: with the pair-averaged metrics mb, mbt and u = mbt + mb.v per node,
 //   F_rho = ({rho u} A + {g}{u})/D,  F_v = {v} F_rho + mb {rho}{T}{g},
@@ -329,7 +351,7 @@ template <int D, int K, int TX, int TY, int TZ> struct FluxLds {
 // PX x PY x TZ block, PX >= TX, PY >= TY (threads outside TX x TY x TZ have no interface).
 // sP: FluxLds<...>::SIZE doubles of LDS.
 // Every thread reaches the internal barrier.
-template <int D, int K, int TX, int TY, int TZ, int PX = TX, int PY = TY>
+template <int D, int K, int TX, int TY, int TZ, int PX = TX, int PY = TY, bool ST = false>
 __device__ __forceinline__ bool flux_tile_eval(const Geo &G, const double *__restrict__ nd, unsigned *flags, int bx0,
                                                int by0, int bz0, double *__restrict__ sP, double (&Fl)[D + 3],
                                                int &a0, int &a1, int &a2) {
@@ -347,35 +369,73 @@ __device__ __forceinline__ bool flux_tile_eval(const Geo &G, const double *__res
   unsigned bad = 0;
 
   // ---- phase 1: pair fluxes of the nodes owning pairs of this tile ----
+  // byte offset of node (i0, i1, i2) in the node buffer; with the step (ST), a solid node next
+  // to the face normal to K stands for the mirror image of its fluid source (mir set)
+  auto node_off = [&](int i0, int i1, int i2, bool &mir) -> unsigned {
+    mir = false;
+    if constexpr (ST) {
+      int src;
+      if (step_image(G, K, i0, i1, src)) {
+        mir = true;
+        if (K == 0) i0 = src;
+        else i1 = src;
+      }
+    }
+    return 8u * (unsigned)(((i2 + G.g[2]) * G.P[1] + (i1 + G.g[1])) * G.P[0] + (i0 + G.g[0]));
+  };
   // item q (local coordinates qx, qy, qz); along K the first item is the node two below the
   // tile's first left node.  Returns false for items whose node lies beyond the grid.
-  auto item_node = [&](int q, unsigned &ob) -> bool {
+  auto item_node = [&](int q, int (&ii)[3]) -> bool {
     const int qx = q % QX, qy = (q / QX) % QY, qz = q / (QX * QY);
-    const int i0 = bx0 + qx - (K == 0 ? 3 : 0), i1 = by0 + qy - (K == 1 ? 3 : 0), i2 = bz0 + qz - (K == 2 ? 3 : 0);
-    const int ik = K == 0 ? i0 : (K == 1 ? i1 : i2);
-    ob = 8u * (unsigned)(((i2 + G.g[2]) * G.P[1] + (i1 + G.g[1])) * G.P[0] + (i0 + G.g[0]));
-    return ik <= G.n[K] - 1 && (K == 0 || i0 < G.n[0]) && (K == 1 || i1 < G.n[1]) && (K == 2 || i2 < G.n[2]);
+    ii[0] = bx0 + qx - (K == 0 ? 3 : 0);
+    ii[1] = by0 + qy - (K == 1 ? 3 : 0);
+    ii[2] = bz0 + qz - (K == 2 ? 3 : 0);
+    const int ik = ii[K];
+    return ik <= G.n[K] - 1 && (K == 0 || ii[0] < G.n[0]) && (K == 1 || ii[1] < G.n[1]) && (K == 2 || ii[2] < G.n[2]);
   };
-  // the pair F(node of item q, node m further along K) into its LDS slots
-  auto pair_to_lds = [&](int q, unsigned ob, const Pq<D> &a, int m) {
+  // node data of item node ii (mirrored if it stands for an image)
+  auto load_item = [&](const int (&ii)[3], unsigned &ob, Pq<D> &a) {
+    bool mir;
+    ob = node_off(ii[0], ii[1], ii[2], mir);
+    load_pq<D, K>(G, nd, ob, a);
+    if (mir) pq_mirror<D, K>(a);
+  };
+  // the pair F(node ii of item q, node m further along K) into its LDS slots
+  auto pair_to_lds = [&](int q, const int (&ii)[3], unsigned ob, const Pq<D> &a, int m) {
     Pq<D> b;
-    load_pq<D, K>(G, nd, ob + 8u * (unsigned)(m * sK), b);
-    double o[NC];
-    ec_pair<D>(G, a, b, o, bad);
+    unsigned bp = 0;
+    if constexpr (ST) {
+      bool mir;
+      const int j0 = ii[0] + (K == 0 ? m : 0), j1 = ii[1] + (K == 1 ? m : 0);
+      load_pq<D, K>(G, nd, node_off(j0, j1, ii[2], mir), b);
+      if (mir) pq_mirror<D, K>(b);
+      double o[NC];
+      ec_pair<D>(G, a, b, o, bp);
+      // only pairs ending at a fluid node enter a flux of the fluid
+      if (!step_solid(G, j0, j1)) bad |= bp;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) sP[(c * 3 + (m - 1)) * Q + q] = o[c];
+      for (int c = 0; c < NC; ++c) sP[(c * 3 + (m - 1)) * Q + q] = o[c];
+    } else {
+      load_pq<D, K>(G, nd, ob + 8u * (unsigned)(m * sK), b);
+      double o[NC];
+      ec_pair<D>(G, a, b, o, bad);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) sP[(c * 3 + (m - 1)) * Q + q] = o[c];
+    }
+    (void)bp;
   };
   constexpr int QK = K == 0 ? QX : (K == 1 ? QY : LQ::QZ);  // items per line along K
   constexpr int NL = Q / QK;                                // lines along K
   if constexpr (Q <= 256 || NL * (QK - 2) != 256) {
     // every item with all three of its pairs, one item per thread and round
     for (int q = tid; q < Q; q += 256) {
+      int ii[3];
+      if (!item_node(q, ii)) continue;
       unsigned ob;
-      if (!item_node(q, ob)) continue;
       Pq<D> a;
-      load_pq<D, K>(G, nd, ob, a);
+      load_item(ii, ob, a);
 #pragma unroll
-      for (int m = 1; m <= 3; ++m) pair_to_lds(q, ob, a, m);
+      for (int m = 1; m <= 3; ++m) pair_to_lds(q, ii, ob, a, m);
     }
   } else {
     // 256 inner items (k-index >= 2 along K), one per thread with its three pairs; then the
@@ -393,12 +453,13 @@ __device__ __forceinline__ bool flux_tile_eval(const Geo &G, const double *__res
         const int r = tid / QX;
         q = ((2 + r / QY) * QY + r % QY) * QX + tid % QX;
       }
-      unsigned ob;
-      if (item_node(q, ob)) {
+      int ii[3];
+      if (item_node(q, ii)) {
+        unsigned ob;
         Pq<D> a;
-        load_pq<D, K>(G, nd, ob, a);
+        load_item(ii, ob, a);
 #pragma unroll
-        for (int m = 1; m <= 3; ++m) pair_to_lds(q, ob, a, m);
+        for (int m = 1; m <= 3; ++m) pair_to_lds(q, ii, ob, a, m);
       }
     }
     for (int u = tid; u < 3 * NL; u += 256) {
@@ -417,11 +478,12 @@ __device__ __forceinline__ bool flux_tile_eval(const Geo &G, const double *__res
         q = ((r == 0 ? 0 : 1) * QY + w % QY) * QX + u % QX;
       }
       const int m = r == 1 ? 2 : 3;
+      int ii[3];
+      if (!item_node(q, ii)) continue;
       unsigned ob;
-      if (!item_node(q, ob)) continue;
       Pq<D> a;
-      load_pq<D, K>(G, nd, ob, a);
-      pair_to_lds(q, ob, a, m);
+      load_item(ii, ob, a);
+      pair_to_lds(q, ii, ob, a, m);
     }
   }
   if (G.diss) {
@@ -432,10 +494,11 @@ __device__ __forceinline__ bool flux_tile_eval(const Geo &G, const double *__res
       // the node buffer holds 3 ghost layers: node indices -3 .. n_K + 2 along K
       bool ok = ik <= G.n[K] + 2 && (K == 0 || i0 < G.n[0]) && (K == 1 || i1 < G.n[1]) && (K == 2 || i2 < G.n[2]);
       if (!ok) continue;
-      const unsigned ob = 8u * (unsigned)(((i2 + G.g[2]) * G.P[1] + (i1 + G.g[1])) * G.P[0] + (i0 + G.g[0]));
+      bool mir;
+      const unsigned ob = node_off(i0, i1, i2, mir);
       sV[q] = ndf(G, nd, F::V1, ob);
 #pragma unroll
-      for (int m = 0; m < D; ++m) sV[(1 + m) * QW + q] = ndf(G, nd, F::V + m, ob);
+      for (int m = 0; m < D; ++m) sV[(1 + m) * QW + q] = (mir && m == K) ? -ndf(G, nd, F::V + m, ob) : ndf(G, nd, F::V + m, ob);
       sV[(D + 1) * QW + q] = ndf(G, nd, F::IT, ob);
     }
   }
@@ -447,7 +510,8 @@ __device__ __forceinline__ bool flux_tile_eval(const Geo &G, const double *__res
   a1 = by0 + ty;
   a2 = bz0 + tz;
   const int e0 = G.n[0] + (K == 0), e1 = G.n[1] + (K == 1), e2 = G.n[2] + (K == 2);
-  if (tx >= TX || ty >= TY || a0 >= e0 || a1 >= e1 || a2 >= e2) {
+  // with the step, a face carries a flux only if its right node (a0, a1) is fluid
+  if (tx >= TX || ty >= TY || a0 >= e0 || a1 >= e1 || a2 >= e2 || (ST && step_solid(G, a0, a1))) {
     if (bad) raise_flag(flags, ESVDW_F_MEANCONSTRAINT);
     return false;
   }
@@ -461,8 +525,13 @@ __device__ __forceinline__ bool flux_tile_eval(const Geo &G, const double *__res
 #pragma unroll
   for (int c = 0; c < NV; ++c) dd[c] = 0.0;
   if (G.diss) {
-    const unsigned pc = 8u * (unsigned)(((i2 + G.g[2]) * G.P[1] + (i1 + G.g[1])) * G.P[0] + (i0 + G.g[0]));
-    const unsigned pr = pc + 8u * (unsigned)sK;
+    // the left node may stand for an image (ST); the right node is fluid
+    bool mirl;
+    const unsigned pc = node_off(i0, i1, i2, mirl);
+    const unsigned pr = ST ? 8u * (unsigned)(((i2 + (K == 2) + G.g[2]) * G.P[1] + (i1 + (K == 1) + G.g[1])) * G.P[0] +
+                                             (i0 + (K == 0) + G.g[0]))
+                           : pc + 8u * (unsigned)sK;
+    const double sl = mirl ? -1.0 : 1.0;  // sign of the left node's normal components
     // (the divisions of the averaged state are grouped so that each group shares one)
     double rl = ndf(G, nd, F::RHO, pc), rr = ndf(G, nd, F::RHO, pr);
     double pl = ndf(G, nd, F::P, pc), pq = ndf(G, nd, F::P, pr);
@@ -477,14 +546,15 @@ __device__ __forceinline__ bool flux_tile_eval(const Geo &G, const double *__res
     const double ilr = il2[0], ilz = il2[1];
     double vb[D];
 #pragma unroll
-    for (int m = 0; m < D; ++m) vb[m] = 0.5 * (ndf(G, nd, F::V + m, pc) + ndf(G, nd, F::V + m, pr));
+    for (int m = 0; m < D; ++m)
+      vb[m] = 0.5 * ((m == K ? sl : 1.0) * ndf(G, nd, F::V + m, pc) + ndf(G, nd, F::V + m, pr));
     double mm[D], L2 = 0.0;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      mm[j] = 0.5 * (ndf(G, nd, F::MS + K * D + j, pc) + ndf(G, nd, F::MS + K * D + j, pr));
+      mm[j] = 0.5 * ((j != K ? sl : 1.0) * ndf(G, nd, F::MS + K * D + j, pc) + ndf(G, nd, F::MS + K * D + j, pr));
       L2 += mm[j] * mm[j];
     }
-    double mtb = 0.5 * (ndf(G, nd, F::XS + K, pc) + ndf(G, nd, F::XS + K, pr));
+    double mtb = 0.5 * (sl * ndf(G, nd, F::XS + K, pc) + ndf(G, nd, F::XS + K, pr));
     double L = sqrt_nr(L2);
     // L(rho) = 1/ilr and 1/L share a division
     const double rLL = rcp_nr(ilr * L);
@@ -571,6 +641,12 @@ __device__ __forceinline__ bool flux_tile_eval(const Geo &G, const double *__res
         for (int c = 0; c < NV; ++c) As[c] = As[c] + A3[c];
       }
     }
+    // zero test of the plain jumps: 2^-40 of the magnitude of all the terms forming W at the two
+    // nodes (a component's own terms can be rounding residue of exact zeros)
+    double zs = 0.0;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) zs += As[c];
+    zs = ldexp(zs, -40);
     double y[NV];
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
@@ -582,8 +658,7 @@ __device__ __forceinline__ bool flux_tile_eval(const Geo &G, const double *__res
       double j0 = W[3][c] - W[2][c];
       const double pd = dp * dm;
       const double jn = fma(j0, pd, np * dm - nm * dp);
-      // a plain jump below the rounding scale of W (2^-40 of its terms) counts as zero
-      if (fabs(j0) <= ldexp(As[c], -40)) j0 = 0.0;
+      if (fabs(j0) <= zs) j0 = 0.0;
       y[c] = ((jn > 0.0 && j0 > 0.0) || (jn < 0.0 && j0 < 0.0)) ? jn * rcp_nr(pd) : 0.0;
     }
     // R y in the rotated frame, then rotate the momentum back (T^T)
@@ -619,13 +694,13 @@ __device__ __forceinline__ bool flux_tile_eval(const Geo &G, const double *__res
 }
 
 // flux_tile_eval, the fluxes written to Fo (component-major, nif interfaces per component)
-template <int D, int K, int TX, int TY, int TZ, int PX = TX, int PY = TY>
+template <int D, int K, int TX, int TY, int TZ, int PX = TX, int PY = TY, bool ST = false>
 __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict__ nd, double *__restrict__ Fo,
                                           long nif, unsigned *flags, int bx0, int by0, int bz0,
                                           double *__restrict__ sP) {
   double Fl[D + 3];
   int a0, a1, a2;
-  if (!flux_tile_eval<D, K, TX, TY, TZ, PX, PY>(G, nd, flags, bx0, by0, bz0, sP, Fl, a0, a1, a2)) return;
+  if (!flux_tile_eval<D, K, TX, TY, TZ, PX, PY, ST>(G, nd, flags, bx0, by0, bz0, sP, Fl, a0, a1, a2)) return;
   const int e0 = G.n[0] + (K == 0), e1 = G.n[1] + (K == 1);
   const long ti = ((long)a2 * e1 + a1) * e0 + a0;
 #pragma unroll

@@ -37,6 +37,7 @@ class Params(ctypes.Structure):
         ("monitor_kind", ctypes.c_int), ("kappa", ctypes.c_int), ("mon_var", ctypes.c_int * 2),
         ("alpha", ctypes.c_double * 3), ("n_filter", ctypes.c_int), ("mu", ctypes.c_int),
         ("mesh_tol", ctypes.c_double), ("fixed_mu", ctypes.c_int), ("walls", ctypes.c_int),
+        ("step", ctypes.c_int * 2), ("inflow", ctypes.c_int), ("inflow_prim", ctypes.c_double * 4),
     ]
 
 
@@ -68,6 +69,14 @@ def params_from(p):
     c.fixed_mu = int(p["fixed_mu"])
     # reflecting walls: (direction, "lo" | "hi") faces of outflow directions
     c.walls = sum(1 << (2 * int(k) + (side == "hi")) for k, side in p.get("walls", ()))
+    # backward-facing step: solid nodes i0 < step[0], i1 < step[1]; inflow: (rho, v1, v2, p) at x_1-lo
+    step = p.get("step")
+    if step:
+        c.step[0], c.step[1] = int(step[0]), int(step[1])
+    if p.get("inflow") is not None:
+        c.inflow = 1
+        for i in range(4):
+            c.inflow_prim[i] = float(p["inflow"][i])
     return c
 
 

@@ -392,6 +392,34 @@ def mach_reflection(p, case, x=None, foot=0.1):
     return np.ascontiguousarray(prim)
 
 
+# Table 5.4 of the paper (Example 5.5, flow over a backward step): (rho, v1, v2, p)_l, (..)_r
+# in the paper's dimensionless units (velocities sqrt(3/8) of the reduced ones), with the
+# printed shock Mach numbers and final times
+TABLE_5_4 = {
+    "TD1": dict(left=(0.85, 0.64, 0.0, 1.01), right=(0.28, 0.0, 0.0, 0.58), mach=1.23, t_end=0.55),
+    "TD2": dict(left=(0.62, -0.14, 0.0, 0.98), right=(0.88, 0.0, 0.0, 1.09), mach=1.05, t_end=1.5),
+}
+
+
+def step_state(case, side):
+    """State `side` ("left" | "right") of Table 5.4 in reduced units: (rho, v1 sqrt(8/3), v2, p)."""
+    rho, u, v, pr = TABLE_5_4[case][side]
+    return (rho, u * math.sqrt(8.0 / 3.0), v * math.sqrt(8.0 / 3.0), pr)
+
+
+def backward_step(p, case, x=None, shock=0.3):
+    """Example 5.5's initial data: the state `left` of Table 5.4 behind a planar shock at
+    x_1 = shock (in the channel above the step), the state `right` everywhere else (the solid
+    nodes included)."""
+    x = nodes_xi(p) if x is None else x
+    left, right = step_state(case, "left"), step_state(case, "right")
+    behind = x[0] < shock
+    prim = np.zeros((4,) + x[0].shape)
+    for v in range(4):
+        prim[v] = np.where(behind, left[v], right[v])
+    return np.ascontiguousarray(prim)
+
+
 def batch_instances(seed, count=256, nmin=64, nmax=384):
     """Independent 2D Riemann instances: n ~ U{nmin..nmax} (square grids), a ~ U[2, 4],
     b ~ U[0.2, 0.4], R = 8/3, c_v = R/0.0125; quadrant states drawn in reduced form and

@@ -1,7 +1,7 @@
 """Pins of the dissipation's sign matrix Y at one interface (Section 3.3, eq. HOstable): Y_m = 1
 exactly where the plain jump [W_m] and the reconstructed jump [W_m]^WENO have the same strict
-sign, else 0; a plain jump at the rounding level of the terms that form W_m (2^-40 of their
-magnitude) counts as zero.
+sign, else 0; a plain jump at the rounding level of the vector W (2^-40 of the magnitude of all
+the terms that form its components at the two nodes) counts as zero.
 
 The oracle reports, per interface, Y, [W]^WENO, the plain jump before its zero test and the
 test's scale (orc_interface_flux).  Independent checks: with dissipation off the same call
