@@ -79,13 +79,13 @@ typedef struct esvdw_params {
   int fixed_mu;         /* 1: exactly mu sweeps; 0: stop once the update is < mesh_tol */
   int walls;            /* ESVDW_WALL_LO / _HI bits (outflow directions only; 0: none) */
   /* Backward-facing step (Example 5.5; 2D, both directions outflow, fixed_mu = 1): the nodes
-   * i0 < step[0], i1 < step[1] form a solid block whose two faces are reflecting walls; the
-   * fluid is the L-shaped rest, with at least 3 nodes beyond the block in each direction.  Seen
-   * along a direction, the 3 solid nodes next to a face stand for the mirror images of the
-   * fluid nodes across it; the solid nodes keep their state (those next to the step hold the
-   * images, for the monitor), the mesh holds the images of the fluid mesh there, and the fluid
-   * nodes of the three 3 x 3 blocks around the corner keep their uniform positions.
-   * step = {0, 0}: no step. */
+   * i0 < step[0], i1 < step[1] (step[k] >= 3) form a solid block whose two faces are
+   * reflecting walls; the fluid is the L-shaped rest, with at least 3 nodes beyond the block in
+   * each direction.  Seen along a direction, the 3 solid nodes next to a face stand for the
+   * mirror images of the fluid nodes across it; the solid nodes keep their state (those next to
+   * the step hold the images, for the monitor), the mesh holds the images of the fluid mesh
+   * there, and the 6 x 6 nodes around the corner form a lattice mirror-symmetric about both
+   * faces (the mesh iteration moves it as a whole).  step = {0, 0}: no step. */
   int step[2];
   int inflow;           /* 1: the lo face of direction 0 (outflow, not a wall; 2D) holds the fixed
                            state inflow_prim in its ghost layers */

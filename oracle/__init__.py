@@ -93,8 +93,8 @@ def make_cfg(p):
     if step:
         if d != 2 or any(BC[p["bc"][k]] != BC["outflow"] for k in range(2)):
             raise ValueError("the step needs a 2D problem with outflow-type directions")
-        if not (0 < step[0] and 0 < step[1] and step[0] + 3 <= c.n[0] and step[1] + 3 <= c.n[1]):
-            raise ValueError("the step needs 3 fluid nodes beyond it in each direction")
+        if not (3 <= step[0] and 3 <= step[1] and step[0] + 3 <= c.n[0] and step[1] + 3 <= c.n[1]):
+            raise ValueError("the step needs 3 solid nodes and 3 fluid nodes beyond it in each direction")
         if not int(p["fixed_mu"]):
             raise ValueError("the step takes the fixed sweep count of the mesh iteration")
         c.step[0], c.step[1] = int(step[0]), int(step[1])

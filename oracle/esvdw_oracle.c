@@ -539,19 +539,6 @@ static int step_image(const orc_cfg *c, int k, int i0, int i1, int *src) {
   return 0;
 }
 
-/* The step's corner couples the images of the two faces: the solid corner block is the image
- * of the fluid block below-right of it across the vertical face and of the fluid block
- * above-left of it across the horizontal one, and the metric stencils of the images near the
- * corner reach those blocks and the fluid block diagonally above-right.  All of these agree
- * when the three 3 x 3 fluid blocks around the corner hold their uniform positions (the mesh
- * iteration does not move them) and the corner block holds its uniform positions too. */
-static int step_held(const orc_cfg *c, int i0, int i1) {
-  if (!has_step(c)) return 0;
-  int s0 = c->step[0], s1 = c->step[1];
-  int near0 = i0 >= s0 - 3 && i0 < s0 + 3, near1 = i1 >= s1 - 3 && i1 < s1 + 3;
-  return near0 && near1 && !solid(c, i0, i1);
-}
-
 /* State at the solid nodes within 3 of a face of the step: the image across that face of its
  * fluid source (normal momentum reversed, J copied); the corner block, within 3 of both
  * faces, takes the image across the vertical face (i0 = step[0]).  These values feed the
@@ -583,22 +570,50 @@ void orc_step_fill_scalar(const orc_cfg *c, double *w) {
       }
 }
 
-/* Mesh at the solid nodes and the held fluid nodes, so that the stencils of the fluid nodes
- * (metrics, monitor, Jacobi sweeps) see the image of the mesh across each face: a solid node
- * within 3 of one face only holds the image of its source (normal coordinate 2 face - x, the
- * other unchanged); the corner block, the held fluid nodes (step_held) and the other solid
- * nodes hold their uniform positions. */
+/* Mesh at the solid nodes and at the corner, so that the stencils of the fluid nodes (metrics,
+ * monitor, Jacobi sweeps) see the image of the mesh across each face.
+ *
+ * The 6 x 6 block of nodes within 3 of the corner along both directions (the solid corner
+ * nodes and the three 3 x 3 fluid blocks left-above, right-above and right-below of the corner)
+ * is a lattice mirror-symmetric about both faces: x_1 = face_1 +- a_m on the columns
+ * step[0] + m and step[0] - 1 - m, x_2 = face_2 +- b_m on the rows step[1] + m and
+ * step[1] - 1 - m (m = 0, 1, 2).  A solid corner node is the image of a fluid node across
+ * the vertical face and of another across the horizontal one, and the metric stencils of the
+ * fluid nodes near the corner use it in both roles; on such a lattice both images are the same
+ * point, so the discrete metric identities and the zero normal flux through both faces hold
+ * exactly.  a_m is the mean of the 9 distances to the vertical face of the fluid nodes of the
+ * block on the two columns of index m (6 on the right, 3 on the left), b_m likewise for the
+ * rows; a lattice is left as it is, up to rounding.
+ *
+ * A solid node within 3 of one face only holds the image of its source (normal coordinate
+ * 2 face - x, the other unchanged); the other solid nodes hold their uniform positions. */
 void orc_step_fill_mesh(const orc_cfg *c, double *x) {
   if (!has_step(c)) return;
   long N = nodes(c);
   int s0 = c->step[0], s1 = c->step[1];
   double face[2] = {c->lo[0] + s0 * dxi(c, 0), c->lo[1] + s1 * dxi(c, 1)};
-  for (int i1 = 0; i1 < s1 + 3; ++i1)
-    for (int i0 = 0; i0 < s0 + 3; ++i0) {
+  double a[3], b[3];
+  for (int m = 0; m < 3; ++m) {
+    double sa = 0.0, sb = 0.0;
+    for (int k = -3; k < 3; ++k) sa += x[iidx(c, s0 + m, s1 + k, 0)] - face[0];
+    for (int k = 0; k < 3; ++k) sa += face[0] - x[iidx(c, s0 - 1 - m, s1 + k, 0)];
+    for (int k = -3; k < 3; ++k) sb += x[N + iidx(c, s0 + k, s1 + m, 0)] - face[1];
+    for (int k = 0; k < 3; ++k) sb += face[1] - x[N + iidx(c, s0 + k, s1 - 1 - m, 0)];
+    a[m] = sa / 9.0;
+    b[m] = sb / 9.0;
+  }
+  for (int i1 = s1 - 3; i1 < s1 + 3; ++i1)
+    for (int i0 = s0 - 3; i0 < s0 + 3; ++i0) {
       long q = iidx(c, i0, i1, 0);
-      if (!solid(c, i0, i1) && !step_held(c, i0, i1)) continue;
+      x[q] = i0 >= s0 ? face[0] + a[i0 - s0] : face[0] - a[s0 - 1 - i0];
+      x[N + q] = i1 >= s1 ? face[1] + b[i1 - s1] : face[1] - b[s1 - 1 - i1];
+    }
+  for (int i1 = 0; i1 < s1; ++i1)
+    for (int i0 = 0; i0 < s0; ++i0) {
+      if (i0 >= s0 - 3 && i1 >= s1 - 3) continue; /* the corner lattice */
+      long q = iidx(c, i0, i1, 0);
       int s, row = step_image(c, 0, i0, i1, &s), col = step_image(c, 1, i0, i1, &s);
-      if (!solid(c, i0, i1) || row == col) { /* held, corner block or deep inside: uniform */
+      if (row == col) { /* deep inside */
         x[q] = c->lo[0] + (i0 + 0.5) * dxi(c, 0);
         x[N + q] = c->lo[1] + (i1 + 0.5) * dxi(c, 1);
         continue;
@@ -1439,7 +1454,7 @@ int orc_jacobi(const orc_cfg *c, const double *omega, double *x, int nsweep, dou
             den += (wp + wm) / h2;
             for (int j = 0; j < d; ++j) num[j] += (wp * xp[j][qpp] + wm * xp[j][qpm]) / h2;
           }
-          const int held = solid(c, i0, i1) || step_held(c, i0, i1); /* set by the fill below */
+          const int held = solid(c, i0, i1); /* set by the fill below */
           for (int j = 0; j < d; ++j) {
             double v = num[j] / den;
             double u = fabs(v - x[j * N + qi]);

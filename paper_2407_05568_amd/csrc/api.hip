@@ -32,7 +32,7 @@ int params_valid(const esvdw_params *p) {
   if (pn * 8.0 >= 4294967296.0) return 0;
   if (p->step[0] != 0 || p->step[1] != 0) {
     if (p->dim != 2 || p->bc[0] != ESVDW_BC_OUTFLOW || p->bc[1] != ESVDW_BC_OUTFLOW || !p->fixed_mu) return 0;
-    if (p->step[0] < 1 || p->step[1] < 1 || p->step[0] + 3 > p->n[0] || p->step[1] + 3 > p->n[1]) return 0;
+    if (p->step[0] < 3 || p->step[1] < 3 || p->step[0] + 3 > p->n[0] || p->step[1] + 3 > p->n[1]) return 0;
   }
   if (p->inflow) {
     if (p->dim != 2 || p->bc[0] != ESVDW_BC_OUTFLOW || (p->walls & ESVDW_WALL_LO(0))) return 0;

@@ -95,11 +95,6 @@ __device__ __forceinline__ bool step_image(const Geo &G, int K, int i0, int i1, 
   }
   return false;
 }
-// fluid nodes held at their uniform positions: the three 3 x 3 blocks around the step's corner
-__device__ __forceinline__ bool step_pinned(const Geo &G, int i0, int i1) {
-  return G.s0 > 0 && i0 >= G.s0 - 3 && i0 < G.s0 + 3 && i1 >= G.s1 - 3 && i1 < G.s1 + 3 && !step_solid(G, i0, i1);
-}
-
 __device__ __forceinline__ long lin(const Geo &G, int i0, int i1, int i2) {
   return ((long)i2 * G.n[1] + i1) * G.n[0] + i0;
 }

@@ -58,26 +58,58 @@ __global__ void k_step_fill_scalar(Geo G, double *__restrict__ w) {
   else if (step_image(G, 1, i0, i1, src)) w[lin(G, i0, i1, 0)] = w[lin(G, i0, src, 0)];
 }
 
-// The mesh: a solid node within 3 of one face only holds the image of its fluid source (normal
-// coordinate 2 face - x, the other unchanged); the corner block, the other solid nodes and the
-// fluid nodes held at the corner (step_pinned) their uniform positions.  One thread per node of
-// the (s0 + 3) x (s1 + 3) rectangle; the sources read are fluid nodes not written here.
+// The mesh.  The 6 x 6 block of nodes within 3 of the corner along both directions is a lattice
+// mirror-symmetric about both faces (x_1 = face_1 +- a_m on the columns s0 + m and s0 - 1 - m,
+// x_2 = face_2 +- b_m on the rows s1 + m and s1 - 1 - m), so that a solid corner node, the image
+// of one fluid node across each face, is the same point in both roles and the discrete metric
+// identities hold at the corner; a_m is the mean distance to the vertical face of the 9 fluid
+// nodes of the block on the two columns of index m, b_m likewise for the rows.  A solid node
+// within 3 of one face only holds the image of its fluid source (normal coordinate 2 face - x,
+// the other unchanged); the other solid nodes their uniform positions.
+// Grid: rows 0 .. s1 - 1 of the solid block, one thread per node outside the corner block
+// (their sources are fluid nodes outside the corner block); the extra row s1, workgroup 0: the
+// corner block, all its reads before a barrier and its writes after it.
 __global__ void k_step_fill_mesh(Geo G, double *__restrict__ x) {
+  const int s0 = G.s0, s1 = G.s1;
+  const double face[2] = {G.lo[0] + s0 * G.dxi[0], G.lo[1] + s1 * G.dxi[1]};
+  if (blockIdx.y == (unsigned)s1) {
+    if (blockIdx.x != 0) return;
+    __shared__ double off[6];  // a_0..a_2, b_0..b_2
+    const int t = threadIdx.x;
+    if (t < 6) {
+      const int m = t % 3, j = t / 3;
+      double sum = 0.0;
+      if (j == 0) {
+        for (int k = -3; k < 3; ++k) sum += x[lin(G, s0 + m, s1 + k, 0)] - face[0];
+        for (int k = 0; k < 3; ++k) sum += face[0] - x[lin(G, s0 - 1 - m, s1 + k, 0)];
+      } else {
+        for (int k = -3; k < 3; ++k) sum += x[G.N + lin(G, s0 + k, s1 + m, 0)] - face[1];
+        for (int k = 0; k < 3; ++k) sum += face[1] - x[G.N + lin(G, s0 + k, s1 - 1 - m, 0)];
+      }
+      off[t] = sum / 9.0;
+    }
+    __syncthreads();
+    if (t < 36) {
+      const int i0 = s0 - 3 + t % 6, i1 = s1 - 3 + t / 6;
+      const long q = lin(G, i0, i1, 0);
+      x[q] = i0 >= s0 ? face[0] + off[i0 - s0] : face[0] - off[s0 - 1 - i0];
+      x[G.N + q] = i1 >= s1 ? face[1] + off[3 + i1 - s1] : face[1] - off[3 + s1 - 1 - i1];
+    }
+    return;
+  }
   const int i0 = blockIdx.x * blockDim.x + threadIdx.x, i1 = blockIdx.y;
-  if (i0 >= G.s0 + 3 || i1 >= G.s1 + 3) return;
-  const bool sol = step_solid(G, i0, i1);
-  if (!sol && !step_pinned(G, i0, i1)) return;
+  if (i0 >= s0 || i1 >= s1 || (i0 >= s0 - 3 && i1 >= s1 - 3)) return;
   const long t = lin(G, i0, i1, 0);
   int s;
   const bool row = step_image(G, 0, i0, i1, s), col = step_image(G, 1, i0, i1, s);
-  if (sol && row != col) {
+  if (row != col) {
     const int k = row ? 0 : 1;
     int src;
     step_image(G, k, i0, i1, src);
     const long ts = k == 0 ? lin(G, src, i1, 0) : lin(G, i0, src, 0);
-    const double face = G.lo[k] + (k == 0 ? G.s0 : G.s1) * G.dxi[k];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) x[(long)j * G.N + t] = j == k ? 2.0 * face - x[(long)j * G.N + ts] : x[(long)j * G.N + ts];
+    for (int j = 0; j < 2; ++j)
+      x[(long)j * G.N + t] = j == k ? 2.0 * face[k] - x[(long)j * G.N + ts] : x[(long)j * G.N + ts];
   } else {
     x[t] = G.lo[0] + (i0 + 0.5) * G.dxi[0];
     x[G.N + t] = G.lo[1] + (i1 + 0.5) * G.dxi[1];
@@ -92,7 +124,7 @@ int launch_step_fill_scalar(const Geo &G, double *w, hipStream_t st) {
 
 int launch_step_fill_mesh(const Geo &G, double *x, hipStream_t st) {
   if (G.s0 <= 0) return 0;
-  hipLaunchKernelGGL(k_step_fill_mesh, dim3(nblk(G.s0 + 3, 64), G.s1 + 3), dim3(64), 0, st, G, x);
+  hipLaunchKernelGGL(k_step_fill_mesh, dim3(nblk(G.s0, 64), G.s1 + 1), dim3(64), 0, st, G, x);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -629,7 +661,7 @@ static int jacobi_d(esvdw_ctx *c, const double *omega, const double *x0, double 
     bool last = it == nsweep - 1 && resid_dev;
     hipLaunchKernelGGL(k_jacobi<D>, g, b, 0, st, G, omega, it == 0 ? a0 : a, o, last ? c->part : nullptr);
     if (last) hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, c->part, nb, c->scal + SC_RESID, 0);
-    if (launch_step_fill_mesh(G, o, st)) return -1;  // the images and held nodes after each sweep
+    if (launch_step_fill_mesh(G, o, st)) return -1;  // the images and the corner lattice after each sweep
     double *tmp = a;
     a = o;
     o = tmp;

@@ -7,7 +7,7 @@ along each).  What the mathematics fixes, and what a mistake in the images, thei
 mesh treatment near the corner breaks:
   * a fluid at rest stays at rest on the adaptive moving mesh (the discrete metric identities
     hold at every fluid node only if the metrics of the images equal the metrics of the imaged
-    mesh, which the held nodes around the corner provide);
+    mesh, which the mirror-symmetric lattice of the 6 x 6 nodes around the corner provides);
   * on a perturbed mesh, the RHS of a fluid at rest is that state times the VCL's dJ (the
     momentum RHS is minus the pressure times the metric identities);
   * a closed L-shaped box conserves mass and energy on the moving mesh;
@@ -94,6 +94,28 @@ def test_closed_l_box_conserves_mass_and_energy(orc):
     for v in (0, 3):
         assert abs(JU[v][fl].sum() - JU0[v][fl].sum()) <= 1e-14 * abs(JU0[v][fl].sum())
     assert np.abs(x - o.uniform_mesh()).max() > 1e-2
+
+
+def test_corner_block_moves_as_a_mirror_symmetric_lattice(orc):
+    """The 6 x 6 nodes around the corner: after moving-mesh steps with a density bump at the
+    corner, x_1 depends on the column only and x_2 on the row only, the columns s0 + m and
+    s0 - 1 - m (rows s1 + m and s1 - 1 - m) lie at equal distances on both sides of the face, and
+    the block has moved."""
+    p = synth.problem(2, [24, 24], bc="outflow", walls=WALLS, step=[8, 8])
+    X, Y = synth.nodes_xi(p)
+    g = np.exp(-((X - 0.36) ** 2 + (Y - 0.38) ** 2) / 0.004)
+    prim = blob(p)
+    prim[0] += 0.2 * g
+    prim[3] += 0.3 * g
+    o, JU, J, x = run(orc, p, prim, 6, True)
+    s0, s1 = p["step"]
+    fx, fy = s0 / 24.0, s1 / 24.0
+    bx, by = x[0][s1 - 3:s1 + 3, s0 - 3:s0 + 3], x[1][s1 - 3:s1 + 3, s0 - 3:s0 + 3]
+    assert np.abs(bx - bx[0]).max() == 0.0 and np.abs(by - by[:, :1]).max() == 0.0
+    assert np.abs((bx[0, 3:] - fx) - (fx - bx[0, 2::-1])).max() < 1e-15
+    assert np.abs((by[3:, 0] - fy) - (fy - by[2::-1, 0])).max() < 1e-15
+    u = o.uniform_mesh()
+    assert np.abs(bx - u[0][s1 - 3:s1 + 3, s0 - 3:s0 + 3]).max() > 1e-3 / 24
 
 
 def test_square_l_box_is_transposition_symmetric(orc):
@@ -195,6 +217,8 @@ def test_step_and_inflow_configuration_checks(orc):
         orc.Oracle(synth.problem(2, [16, 16], bc="periodic", step=[4, 4]))
     with pytest.raises(ValueError):
         orc.Oracle(synth.problem(2, [16, 16], bc="outflow", step=[14, 4]))
+    with pytest.raises(ValueError):
+        orc.Oracle(synth.problem(2, [16, 16], bc="outflow", step=[2, 4]))
     with pytest.raises(ValueError):
         orc.Oracle(synth.problem(2, [16, 16], bc="outflow", walls=[(0, "lo")], inflow=[1, 0, 0, 1]))
     with pytest.raises(ValueError):
