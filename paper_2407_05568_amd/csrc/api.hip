@@ -270,7 +270,8 @@ int redistribute_mesh(esvdw_ctx *c, const double *JU, const double *J, const dou
   if (!c || !JU || !J || !x_n || !xdot || !dt_dev) return ESVDW_EINVAL;
   const esvdw_params &p = c->p;
   long n = (long)c->G.dim * c->G.N;
-  if (launch_monitor(c, JU, J, c->omega, st)) return ESVDW_EHIP;
+  long nbc = 0;  // the CFL partials formed with the monitor (2D), else 0
+  if (launch_monitor_cfl(c, JU, J, x_n, c->omega, &nbc, st)) return ESVDW_EHIP;
   // x^[0] = x_n (+ warm_dx); with a fixed sweep count and no warm start the first sweep reads x_n
   const bool from_xn = p.fixed_mu && !warm_dx;
   if (warm_dx) {
@@ -302,7 +303,7 @@ int redistribute_mesh(esvdw_ctx *c, const double *JU, const double *J, const dou
     if (resid_dev && launch_copy(c->scal + SC_N - 1, resid_dev, 1, st)) return ESVDW_EHIP;
   }
   if (sweeps_dev && launch_set_int(sweeps_dev, sweeps, st)) return ESVDW_EHIP;
-  if (launch_limiter_cfl(c, x_n, c->xmu, JU, J, dt_dev, st)) return ESVDW_EHIP;
+  if (launch_limiter_cfl(c, x_n, c->xmu, JU, J, dt_dev, nbc, st)) return ESVDW_EHIP;
   if (launch_xdot(c, x_n, c->xmu, c->scal + SC_GAMMA, dt_dev, xdot, st)) return ESVDW_EHIP;
   return ESVDW_OK;
 }

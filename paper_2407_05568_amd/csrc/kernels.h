@@ -24,6 +24,8 @@ int launch_set_int(int *p, int v, hipStream_t st);
 
 int launch_set_scalars(esvdw_ctx *c, hipStream_t st);
 int launch_monitor(esvdw_ctx *c, const double *JU, const double *J, double *omega, hipStream_t st);
+int launch_monitor_cfl(esvdw_ctx *c, const double *JU, const double *J, const double *xn, double *omega, long *nbc,
+                       hipStream_t st);
 int launch_jacobi(esvdw_ctx *c, const double *omega, double *x, int nsweep, double *resid_dev, hipStream_t st);
 // nsweep sweeps from the iterate x0 (not modified; nullptr = x), the result in x
 int launch_jacobi_from(esvdw_ctx *c, const double *omega, const double *x0, double *x, int nsweep, double *resid_dev,
@@ -34,7 +36,7 @@ int launch_limiter(esvdw_ctx *c, const double *xn, const double *xmu, double *ga
 // launch_limiter (gamma into the context's scalars) followed by launch_cfl, the two final
 // reductions in one launch
 int launch_limiter_cfl(esvdw_ctx *c, const double *xn, const double *xmu, const double *JU, const double *J,
-                       double *dt_dev, hipStream_t st);
+                       double *dt_dev, long nbc_ready, hipStream_t st);
 int launch_cfl(esvdw_ctx *c, const double *JU, const double *J, const double *x, double *dt_dev, hipStream_t st);
 // launch_cfl on the library's static per-device scratch (1D/2D); returns an ESVDW_* code
 int launch_cfl_noalloc(const Geo &G, double cfl, double dt_fixed, const double *JU, const double *J,

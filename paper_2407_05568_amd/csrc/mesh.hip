@@ -190,7 +190,8 @@ __global__ void k_jacobi(Geo G, const double *__restrict__ omega, const double *
 // updated: the first ghost layer (the only one a 5-point update reads) is refreshed after every
 // sweep as the mirror image of the wall node (normal coordinate 2 wall - x, tangential x),
 // exactly as mesh_at forms it; omega ghosts are static.  The per-node arithmetic is
-// jacobi_point's, term for term, so the mesh equals nsw launches of k_jacobi bit for bit.
+// jacobi_point's, term for term (both with contraction off and their fused multiply-adds
+// written out), so the mesh equals nsw launches of k_jacobi bit for bit.
 // Periodic directions are not handled (the launcher falls back to k_jacobi).
 constexpr int JT_X = 54, JT_Y = 10, JT_H = 5;
 constexpr int JT_EX = JT_X + 2 * JT_H, JT_EY = JT_Y + 2 * JT_H, JT_NE = JT_EX * JT_EY;
@@ -199,6 +200,7 @@ static_assert(JT_EX <= 64, "one extended row per 64-lane row of threads");
 __global__ void __launch_bounds__(256) k_jacobi_multi2(Geo G, const double *__restrict__ omega,
                                                        const double *__restrict__ xin, double *__restrict__ xout,
                                                        int nsw, double *part) {
+#pragma clang fp contract(off)
   __shared__ double sw[JT_NE], sx[2][2][JT_NE];
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
   const int exn = JT_X + 2 * nsw, eyn = JT_Y + 2 * nsw;
@@ -239,32 +241,50 @@ __global__ void __launch_bounds__(256) k_jacobi_multi2(Geo G, const double *__re
   const bool wall = cl >= 0 || cr >= 0 || rb >= 0 || rt >= 0;
   double r = 0.0;
   int cur = 0;
+  // omega does not change between sweeps: the face weights and 1/den of the thread's rows
+  // (ey = ty + 4 j) are formed once, with jacobi_point's arithmetic
+  constexpr int NR = (JT_EY + 3) / 4;
+  double wx[NR][2], wy[NR][2], iden[NR];
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    const int ey = ty + 4 * j;
+    wx[j][0] = wx[j][1] = wy[j][0] = wy[j][1] = iden[j] = 0.0;
+    if (tx >= 1 && tx < exn - 1 && ey >= 1 && ey < eyn - 1) {
+      const int e = ey * exn + tx;
+      const double w0 = sw[e];
+      double den = 0.0;
+      wx[j][0] = 0.5 * (w0 + sw[e + 1]) * h2x;
+      wx[j][1] = 0.5 * (w0 + sw[e - 1]) * h2x;
+      den += wx[j][0] + wx[j][1];
+      wy[j][0] = 0.5 * (w0 + sw[e + exn]) * h2y;
+      wy[j][1] = 0.5 * (w0 + sw[e - exn]) * h2y;
+      den += wy[j][0] + wy[j][1];
+      iden[j] = 1.0 / den;
+    }
+  }
   for (int s = 1; s <= nsw; ++s) {
     const double *A0 = sx[cur][0], *A1 = sx[cur][1];
     double *B0 = sx[cur ^ 1][0], *B1 = sx[cur ^ 1][1];
     if (tx >= s && tx < exn - s && inx)
-      for (int ey = s + ty; ey < eyn - s; ey += 4) {
+#pragma unroll
+      for (int j = 0; j < NR; ++j) {
+        const int ey = ty + 4 * j;
+        if (ey < s || ey >= eyn - s) continue;
         const int gy = gy0 + ey;
         if (gy < 0 || gy >= n1) continue;
         const int e = ey * exn + tx;
-        const double w0 = sw[e];
-        double den = 0.0, num0 = 0.0, num1 = 0.0;
+        double num0 = 0.0, num1 = 0.0;
         {  // direction 0, as jacobi_point with k = 0
-          const double wp = 0.5 * (w0 + sw[e + 1]) * h2x;
-          const double wm = 0.5 * (w0 + sw[e - 1]) * h2x;
-          den += wp + wm;
-          num0 += wp * A0[e + 1] + wm * A0[e - 1];
-          num1 += wp * A1[e + 1] + wm * A1[e - 1];
+          const double wp = wx[j][0], wm = wx[j][1];
+          num0 += fma(wp, A0[e + 1], wm * A0[e - 1]);
+          num1 += fma(wp, A1[e + 1], wm * A1[e - 1]);
         }
         {  // direction 1
-          const double wp = 0.5 * (w0 + sw[e + exn]) * h2y;
-          const double wm = 0.5 * (w0 + sw[e - exn]) * h2y;
-          den += wp + wm;
-          num0 += wp * A0[e + exn] + wm * A0[e - exn];
-          num1 += wp * A1[e + exn] + wm * A1[e - exn];
+          const double wp = wy[j][0], wm = wy[j][1];
+          num0 += fma(wp, A0[e + exn], wm * A0[e - exn]);
+          num1 += fma(wp, A1[e + exn], wm * A1[e - exn]);
         }
-        const double iden = 1.0 / den;
-        const double v0 = num0 * iden, v1 = num1 * iden;
+        const double v0 = num0 * iden[j], v1 = num1 * iden[j];
         if (s == nsw) r = fmax(r, fmax(fabs(v0 - A0[e]), fabs(v1 - A1[e])));
         B0[e] = v0;
         B1[e] = v1;
@@ -492,6 +512,67 @@ __global__ void __launch_bounds__(256) k_cfl_t2(Geo G, const double *__restrict_
   if (flat_tid() == 0) part[flat_bid()] = bm;
 }
 
+// 2D without a step: the monitor terms of U^n (k_rho_G + k_mon_terms) and the CFL maxima on x^n
+// (k_cfl_t2) in one pass over the state.  rho and G of the tile with a 1-node halo and the mesh of
+// the tile with a 3-node halo are staged in LDS; a block of 64 x 4 threads covers 64 x 8 nodes,
+// two rows per thread.  The per-node values are those of rhoG_point, mon_terms_point and
+// cfl_rate_m, so the terms, their maxima and the CFL maximum equal the separate kernels'.
+#define MC_TX 64
+#define MC_TY 8
+__global__ void __launch_bounds__(256) k_mon_cfl_t2(Geo G, int kind, int kappa, int var0, int var1,
+                                                    const double *__restrict__ JU, const double *__restrict__ J,
+                                                    const double *__restrict__ x, double *__restrict__ term,
+                                                    double *part, long npart, double *pc) {
+  constexpr int RW = MC_TX + 2, RS = RW * (MC_TY + 2);
+  __shared__ MeshTile2<MC_TX, MC_TY> T;
+  __shared__ double sRG[2][RS];
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
+  const int b0 = blockIdx.x * MC_TX, b1 = blockIdx.y * MC_TY;
+  const long bid = (long)blockIdx.y * gridDim.x + blockIdx.x;
+  mesh_tile_fill<MC_TX, MC_TY>(G, x, nullptr, 0.0, b0, b1, T, tid, 256);
+  for (int idx = tid; idx < RS; idx += 256) {
+    const int i0 = b0 - 1 + idx % RW, i1 = b1 - 1 + idx / RW;
+    double rho = 0.0, g = 0.0;
+    // a neighbour outside the grid is the node state_index maps it to, as in mon_terms_point
+    if (i0 >= -1 && i0 <= G.n[0] && i1 >= -1 && i1 <= G.n[1]) rhoG_vals<2>(G, JU, J, state_index(G, i0, i1, 0), rho, g);
+    sRG[0][idx] = rho;
+    sRG[1][idx] = g;
+  }
+  __syncthreads();
+  const int nterm = kind == ESVDW_MON_VDW ? kappa + 1 : 2;
+  double mx[3] = {0.0, 0.0, 0.0}, mc = 0.0;
+#pragma unroll
+  for (int r = 0; r < MC_TY / 4; ++r) {
+    const int u = tx, v = ty + 4 * r;
+    const int i0 = b0 + u, i1 = b1 + v;
+    if (i0 >= G.n[0] || i1 >= G.n[1]) continue;
+    const long t = (long)i1 * G.n[0] + i0;
+    const int e = (v + 1) * RW + u + 1;
+    for (int q = 0; q < nterm; ++q) {
+      int field;
+      bool second;
+      mon_term_kind(kind, kappa, var0, var1, q, field, second);
+      const double *f = sRG[field];
+      double s2 = 0.0;
+      s2 += mon_term_part(f[e + 1], f[e], f[e - 1], G.idxi[0], second);
+      s2 += mon_term_part(f[e + RW], f[e], f[e - RW], G.idxi[1], second);
+      const double val = kind == ESVDW_MON_VDW ? s2 : sqrt(s2);
+      term[(long)q * G.N + t] = val;
+      mx[q] = fmax(mx[q], val);
+    }
+    double m[2][2];
+    mesh_tile_metrics<MC_TX, MC_TY>(G, T, u, v, m);
+    mc = fmax(mc, cfl_rate_m<2>(G, JU, J, t, m));
+  }
+  for (int q = 0; q < 3; ++q) {
+    if (q >= nterm) break;
+    const double bm = block_max(mx[q]);
+    if (tid == 0) part[q * npart + bid] = bm;
+  }
+  const double bc = block_max(mc);
+  if (tid == 0) pc[bid] = bc;
+}
+
 static inline void cfl_launch(esvdw_ctx *c, const double *JU, const double *J, const double *x, double *part,
                               long &nb, hipStream_t st) {
   const Geo &G = c->G;
@@ -586,16 +667,29 @@ int launch_add(const double *a, const double *b, double *dst, long n, hipStream_
   return CHK();
 }
 
-template <int D> static int monitor_d(esvdw_ctx *c, const double *JU, const double *J, double *omega, hipStream_t st) {
+// xn != nullptr (2D without a step): the CFL partial maxima of (JU, J) on xn are formed in the same
+// pass (k_mon_cfl_t2) into part + 3 npart, their block count into *nbc; otherwise *nbc = 0
+template <int D>
+static int monitor_d(esvdw_ctx *c, const double *JU, const double *J, const double *xn, double *omega, long *nbc,
+                     hipStream_t st) {
   const Geo &G = c->G;
   const esvdw_params &p = c->p;
   dim3 b, g;
   node_grid(G.n[0], G.n[1], G.n[2], g, b);
-  const long nb = (long)g.x * g.y * g.z;
-  hipLaunchKernelGGL(k_rho_G<D>, g, b, 0, st, G, JU, J, c->rhoG);
+  long nb = (long)g.x * g.y * g.z;
   int nterm = p.monitor_kind == ESVDW_MON_VDW ? p.kappa + 1 : 2;
-  hipLaunchKernelGGL(k_mon_terms<D>, g, b, 0, st, G, p.monitor_kind, p.kappa, p.mon_var[0], p.mon_var[1], c->rhoG,
-                     c->mterm, c->part, c->npart);
+  if (nbc) *nbc = 0;
+  if (D == 2 && xn && nbc && G.s0 == 0) {
+    const dim3 gt((G.n[0] + MC_TX - 1) / MC_TX, (G.n[1] + MC_TY - 1) / MC_TY, 1);
+    nb = (long)gt.x * gt.y;  // <= npart
+    hipLaunchKernelGGL(k_mon_cfl_t2, gt, dim3(64, 4, 1), 0, st, G, p.monitor_kind, p.kappa, p.mon_var[0],
+                       p.mon_var[1], JU, J, xn, c->mterm, c->part, c->npart, c->part + 3 * c->npart);
+    *nbc = nb;
+  } else {
+    hipLaunchKernelGGL(k_rho_G<D>, g, b, 0, st, G, JU, J, c->rhoG);
+    hipLaunchKernelGGL(k_mon_terms<D>, g, b, 0, st, G, p.monitor_kind, p.kappa, p.mon_var[0], p.mon_var[1], c->rhoG,
+                       c->mterm, c->part, c->npart);
+  }
   hipLaunchKernelGGL(k_final_many, dim3(nterm), dim3(1024), 0, st, c->part, c->npart, nb, c->scal + SC_MON);
   // 2D outflow grids run up to JT_H passes per launch; the filtered result must end in `omega`:
   // start in omega2 when the launch count is odd
@@ -623,9 +717,18 @@ template <int D> static int monitor_d(esvdw_ctx *c, const double *JU, const doub
 
 int launch_monitor(esvdw_ctx *c, const double *JU, const double *J, double *omega, hipStream_t st) {
   switch (c->G.dim) {
-    case 1: return monitor_d<1>(c, JU, J, omega, st);
-    case 2: return monitor_d<2>(c, JU, J, omega, st);
-    default: return monitor_d<3>(c, JU, J, omega, st);
+    case 1: return monitor_d<1>(c, JU, J, nullptr, omega, nullptr, st);
+    case 2: return monitor_d<2>(c, JU, J, nullptr, omega, nullptr, st);
+    default: return monitor_d<3>(c, JU, J, nullptr, omega, nullptr, st);
+  }
+}
+
+int launch_monitor_cfl(esvdw_ctx *c, const double *JU, const double *J, const double *xn, double *omega, long *nbc,
+                       hipStream_t st) {
+  switch (c->G.dim) {
+    case 1: return monitor_d<1>(c, JU, J, xn, omega, nbc, st);
+    case 2: return monitor_d<2>(c, JU, J, xn, omega, nbc, st);
+    default: return monitor_d<3>(c, JU, J, xn, omega, nbc, st);
   }
 }
 
@@ -790,7 +893,7 @@ int launch_cfl_noalloc(const Geo &G, double cfl, double dt_fixed, const double *
 }
 
 int launch_limiter_cfl(esvdw_ctx *c, const double *xn, const double *xmu, const double *JU, const double *J,
-                       double *dt_dev, hipStream_t st) {
+                       double *dt_dev, long nbc_ready, hipStream_t st) {
   const Geo &G = c->G;
   if (c->p.dt_fixed > 0.0) {
     if (launch_limiter(c, xn, xmu, nullptr, st)) return -1;
@@ -804,8 +907,8 @@ int launch_limiter_cfl(esvdw_ctx *c, const double *xn, const double *xmu, const 
   else if (G.dim == 2) hipLaunchKernelGGL(k_limiter<2>, g, b, 0, st, G, xn, xmu, c->part);
   else hipLaunchKernelGGL(k_limiter<3>, g, b, 0, st, G, xn, xmu, c->part);
   if (G.dim == 3 && launch_metrics(c, xn, nullptr, c->met, nullptr, nullptr, st)) return -1;
-  long nbc = 0;
-  cfl_launch(c, JU, J, xn, pc, nbc, st);
+  long nbc = nbc_ready;  // > 0: the CFL partials of (JU, J) on xn are already in pc (launch_monitor_cfl)
+  if (nbc == 0) cfl_launch(c, JU, J, xn, pc, nbc, st);
   hipLaunchKernelGGL(k_final_gamma_dt, dim3(1), dim3(1024), 0, st, c->part, nb, pc, nbc, c->p.cfl, c->scal, dt_dev);
   return CHK();
 }

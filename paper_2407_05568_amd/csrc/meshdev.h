@@ -7,17 +7,49 @@
 
 // (rho, G) at interior node t
 template <int D>
-__device__ __forceinline__ void rhoG_point(const Geo &G, const double *__restrict__ JU, const double *__restrict__ J,
-                                           double *__restrict__ rg, long t) {
+__device__ __forceinline__ void rhoG_vals(const Geo &G, const double *__restrict__ JU, const double *__restrict__ J,
+                                          long t, double &rho, double &g) {
   double iJ = 1.0 / J[t];
-  double rho = JU[t] * iJ, v2 = 0.0;
+  double v2 = 0.0;
+  rho = JU[t] * iJ;
   for (int m = 0; m < D; ++m) {
     double v = JU[(long)(1 + m) * G.N + t] * iJ / rho;
     v2 += v * v;
   }
   double T = eos_T_rho_e(G, rho, JU[(long)(D + 1) * G.N + t] * iJ / rho - 0.5 * v2);
+  g = eos_G(G, rho, T);
+}
+template <int D>
+__device__ __forceinline__ void rhoG_point(const Geo &G, const double *__restrict__ JU, const double *__restrict__ J,
+                                           double *__restrict__ rg, long t) {
+  double rho, g;
+  rhoG_vals<D>(G, JU, J, t, rho, g);
   rg[t] = rho;
-  rg[G.N + t] = eos_G(G, rho, T);
+  rg[G.N + t] = g;
+}
+
+// which field term q of the monitor differentiates (0: rho, 1: G) and whether by the Laplacian
+// (second differences) instead of the gradient
+__device__ __forceinline__ void mon_term_kind(int kind, int kappa, int var0, int var1, int q, int &field,
+                                              bool &second) {
+  if (kind == ESVDW_MON_VDW) {
+    if (q < kappa) {
+      field = (q == 0 ? var0 : var1) == ESVDW_VAR_G ? 1 : 0;
+      second = false;
+    } else {
+      field = 1;
+      second = true;
+    }
+  } else {
+    field = 0;
+    second = q == 1;
+  }
+}
+
+// one direction's contribution to a monitor term from the centre value f0 and the neighbours fp, fm
+__device__ __forceinline__ double mon_term_part(double fp, double f0, double fm, double idxi, bool second) {
+  const double g = second ? (fp - 2.0 * f0 + fm) * idxi * idxi : (fp - fm) * 0.5 * idxi;
+  return g * g;
 }
 
 // the monitor terms at node (i0, i1, i2) into term[q N + t] and val[q]; returns the term count
@@ -28,28 +60,17 @@ __device__ __forceinline__ int mon_terms_point(const Geo &G, int kind, int kappa
   const long t = lin(G, i0, i1, i2);
   int nterm = kind == ESVDW_MON_VDW ? kappa + 1 : 2;
   for (int q = 0; q < nterm; ++q) {
-    const double *f;
+    int field;
     bool second;
-    if (kind == ESVDW_MON_VDW) {
-      if (q < kappa) {
-        f = ((q == 0 ? var0 : var1) == ESVDW_VAR_G) ? rg + G.N : rg;
-        second = false;
-      } else {
-        f = rg + G.N;
-        second = true;
-      }
-    } else {
-      f = rg;
-      second = q == 1;
-    }
+    mon_term_kind(kind, kappa, var0, var1, q, field, second);
+    const double *f = rg + (long)field * G.N;
     double f0 = f[t], s2 = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       int e0 = k == 0, e1 = k == 1, e2 = k == 2;
       double fp = f[state_index(G, i0 + e0, i1 + e1, i2 + e2)];
       double fm = f[state_index(G, i0 - e0, i1 - e1, i2 - e2)];
-      double g = second ? (fp - 2.0 * f0 + fm) * G.idxi[k] * G.idxi[k] : (fp - fm) * 0.5 * G.idxi[k];
-      s2 += g * g;
+      s2 += mon_term_part(fp, f0, fm, G.idxi[k], second);
     }
     val[q] = kind == ESVDW_MON_VDW ? s2 : sqrt(s2);
     term[(long)q * G.N + t] = val[q];
@@ -91,6 +112,8 @@ template <int D>
 __device__ __forceinline__ double jacobi_point(const Geo &G, const double *__restrict__ omega,
                                               const double *__restrict__ xin, double *__restrict__ xout, int i0,
                                               int i1, int i2) {
+  // no contraction here: k_jacobi_multi2 repeats this arithmetic and must give the same bits
+#pragma clang fp contract(off)
   const long t = lin(G, i0, i1, i2);
   double w0 = omega[t];
   double den = 0.0, num[D];
@@ -105,8 +128,8 @@ __device__ __forceinline__ double jacobi_point(const Geo &G, const double *__res
     den += wp + wm;
 #pragma unroll
     for (int j = 0; j < D; ++j)
-      num[j] += wp * mesh_at(G, xin, j, i0 + e0, i1 + e1, i2 + e2, 0) +
-                wm * mesh_at(G, xin, j, i0 - e0, i1 - e1, i2 - e2, 0);
+      num[j] += fma(wp, mesh_at(G, xin, j, i0 + e0, i1 + e1, i2 + e2, 0),
+                    wm * mesh_at(G, xin, j, i0 - e0, i1 - e1, i2 - e2, 0));
   }
   double iden = 1.0 / den, r = 0.0;
 #pragma unroll

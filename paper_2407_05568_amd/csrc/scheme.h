@@ -138,6 +138,11 @@ __device__ __forceinline__ void node_point(const Geo &G, const double *__restric
       nd[(long)(F::XS + k) * G.PN + t] = xv;
     }
   } else {
+    // the mesh velocity first: with its loads after the nine 3D metrics the compiler kept
+    // twice the registers and spilled 436 bytes per lane
+    double xv[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) xv[j] = xd ? mesh_at(G, xd, j, i0, i1, i2, 1) : 0.0;
     double m[D][D];
     if constexpr (D == 2) {
       metrics2(G, xn, xd, cdt, i0, i1, m);
@@ -147,9 +152,6 @@ __device__ __forceinline__ void node_point(const Geo &G, const double *__restric
 #pragma unroll
         for (int j = 0; j < D; ++j) m[k][j] = metric_at<D>(G, xn, xd, cdt, dp, dpN, k, j, i0, i1, i2);
     }
-    double xv[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) xv[j] = xd ? mesh_at(G, xd, j, i0, i1, i2, 1) : 0.0;
     node_metrics_store<D>(G, nd, t, m, xv);
   }
 }
