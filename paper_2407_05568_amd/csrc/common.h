@@ -326,6 +326,21 @@ __device__ __forceinline__ double eos_G(const Geo &G, double rho, double T) {
   double ob = 1.0 - G.b * rho;
   return ((1.0 + G.delta) * (2.0 + G.delta) * G.R * T / (ob * ob * ob) - 6.0 * G.a * rho) / (2.0 * eos_c2(G, rho, T));
 }
+// 1/J, rho, v and T of interior node t (the monitor's rho and G come from the same values)
+template <int D>
+__device__ __forceinline__ void node_prim(const Geo &G, const double *__restrict__ JU, const double *__restrict__ J,
+                                          long t, double &iJ, double &rho, double (&v)[D], double &T) {
+  iJ = 1.0 / J[t];
+  rho = JU[t] * iJ;
+  double v2 = 0.0;
+#pragma unroll
+  for (int m = 0; m < D; ++m) {
+    v[m] = JU[(long)(1 + m) * G.N + t] * iJ / rho;
+    v2 += v[m] * v[m];
+  }
+  T = eos_T_rho_e(G, rho, JU[(long)(D + 1) * G.N + t] * iJ / rho - 0.5 * v2);
+}
+
 // eq. coefflimit / eq. Tlimit
 __device__ __forceinline__ bool admissible(const Geo &G, double rho, double T) {
   double ob = 1.0 - G.b * rho;

@@ -513,10 +513,12 @@ __global__ void __launch_bounds__(256) k_cfl_t2(Geo G, const double *__restrict_
 }
 
 // 2D without a step: the monitor terms of U^n (k_rho_G + k_mon_terms) and the CFL maxima on x^n
-// (k_cfl_t2) in one pass over the state.  rho and G of the tile with a 1-node halo and the mesh of
-// the tile with a 3-node halo are staged in LDS; a block of 64 x 4 threads covers 64 x 8 nodes,
-// two rows per thread.  The per-node values are those of rhoG_point, mon_terms_point and
-// cfl_rate_m, so the terms, their maxima and the CFL maximum equal the separate kernels'.
+// (k_cfl_t2) in one pass over the state.  The mesh of the tile with a 3-node halo is staged in
+// LDS first; then each node of the tile and its 1-node halo gets its primitive values once, which
+// give rho and G (staged in LDS for the monitor's differences) and, at the tile's own nodes, the
+// CFL sum.  A block of 64 x 4 threads covers 64 x 8 nodes.  The per-node values are those of
+// rhoG_point, mon_terms_point and cfl_rate_m, so the terms, their maxima and the CFL maximum
+// equal the separate kernels'.
 #define MC_TX 64
 #define MC_TY 8
 __global__ void __launch_bounds__(256) k_mon_cfl_t2(Geo G, int kind, int kappa, int var0, int var1,
@@ -530,17 +532,28 @@ __global__ void __launch_bounds__(256) k_mon_cfl_t2(Geo G, int kind, int kappa, 
   const int b0 = blockIdx.x * MC_TX, b1 = blockIdx.y * MC_TY;
   const long bid = (long)blockIdx.y * gridDim.x + blockIdx.x;
   mesh_tile_fill<MC_TX, MC_TY>(G, x, nullptr, 0.0, b0, b1, T, tid, 256);
+  __syncthreads();
+  double mc = 0.0;
   for (int idx = tid; idx < RS; idx += 256) {
-    const int i0 = b0 - 1 + idx % RW, i1 = b1 - 1 + idx / RW;
+    const int a = idx % RW, b = idx / RW, i0 = b0 - 1 + a, i1 = b1 - 1 + b;
     double rho = 0.0, g = 0.0;
     // a neighbour outside the grid is the node state_index maps it to, as in mon_terms_point
-    if (i0 >= -1 && i0 <= G.n[0] && i1 >= -1 && i1 <= G.n[1]) rhoG_vals<2>(G, JU, J, state_index(G, i0, i1, 0), rho, g);
+    if (i0 >= -1 && i0 <= G.n[0] && i1 >= -1 && i1 <= G.n[1]) {
+      double iJ, v[2], Tn;
+      node_prim<2>(G, JU, J, state_index(G, i0, i1, 0), iJ, rho, v, Tn);
+      g = eos_G(G, rho, Tn);
+      if (a >= 1 && a <= MC_TX && b >= 1 && b <= MC_TY && i0 < G.n[0] && i1 < G.n[1]) {  // a node of the tile
+        double m[2][2];
+        mesh_tile_metrics<MC_TX, MC_TY>(G, T, a - 1, b - 1, m);
+        mc = fmax(mc, cfl_rate_prim<2>(G, iJ, rho, v, Tn, m));
+      }
+    }
     sRG[0][idx] = rho;
     sRG[1][idx] = g;
   }
   __syncthreads();
   const int nterm = kind == ESVDW_MON_VDW ? kappa + 1 : 2;
-  double mx[3] = {0.0, 0.0, 0.0}, mc = 0.0;
+  double mx[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int r = 0; r < MC_TY / 4; ++r) {
     const int u = tx, v = ty + 4 * r;
@@ -560,9 +573,6 @@ __global__ void __launch_bounds__(256) k_mon_cfl_t2(Geo G, int kind, int kappa, 
       term[(long)q * G.N + t] = val;
       mx[q] = fmax(mx[q], val);
     }
-    double m[2][2];
-    mesh_tile_metrics<MC_TX, MC_TY>(G, T, u, v, m);
-    mc = fmax(mc, cfl_rate_m<2>(G, JU, J, t, m));
   }
   for (int q = 0; q < 3; ++q) {
     if (q >= nterm) break;

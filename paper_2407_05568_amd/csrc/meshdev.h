@@ -9,14 +9,8 @@
 template <int D>
 __device__ __forceinline__ void rhoG_vals(const Geo &G, const double *__restrict__ JU, const double *__restrict__ J,
                                           long t, double &rho, double &g) {
-  double iJ = 1.0 / J[t];
-  double v2 = 0.0;
-  rho = JU[t] * iJ;
-  for (int m = 0; m < D; ++m) {
-    double v = JU[(long)(1 + m) * G.N + t] * iJ / rho;
-    v2 += v * v;
-  }
-  double T = eos_T_rho_e(G, rho, JU[(long)(D + 1) * G.N + t] * iJ / rho - 0.5 * v2);
+  double iJ, v[D], T;
+  node_prim<D>(G, JU, J, t, iJ, rho, v, T);
   g = eos_G(G, rho, T);
 }
 template <int D>

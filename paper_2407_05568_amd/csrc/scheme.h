@@ -788,18 +788,11 @@ __device__ __forceinline__ void update_point(const Geo &G, const double *__restr
 // CFL spectral-radius sum at node (i0, i1, i2): sum_k (|v . m_k| + |m_k| c) / (J dxi_k) with
 // m_k = J grad xi_k; metrics of the mesh x computed in place (1D/2D) or read from met (3D)
 // the same sum with the metrics mm[k][j] of the node given
+// the CFL sum from a node's primitive values and metrics
 template <int D>
-__device__ __forceinline__ double cfl_rate_m(const Geo &G, const double *__restrict__ JU, const double *__restrict__ J,
-                                             long t, const double (&mm)[D][D]) {
+__device__ __forceinline__ double cfl_rate_prim(const Geo &G, double iJ, double rho, const double (&v)[D], double T,
+                                                const double (&mm)[D][D]) {
   double s = 0.0;
-  double iJ = 1.0 / J[t];
-  double rho = JU[t] * iJ, v[D], v2 = 0.0;
-#pragma unroll
-  for (int m = 0; m < D; ++m) {
-    v[m] = JU[(long)(1 + m) * G.N + t] * iJ / rho;
-    v2 += v[m] * v[m];
-  }
-  double T = eos_T_rho_e(G, rho, JU[(long)(D + 1) * G.N + t] * iJ / rho - 0.5 * v2);
   double c = sqrt(eos_c2(G, rho, T));
 #pragma unroll
   for (int k = 0; k < D; ++k) {
@@ -813,6 +806,14 @@ __device__ __forceinline__ double cfl_rate_m(const Geo &G, const double *__restr
     s += (fabs(vn) + sqrt(L2) * c) * iJ * G.idxi[k];
   }
   return s;
+}
+
+template <int D>
+__device__ __forceinline__ double cfl_rate_m(const Geo &G, const double *__restrict__ JU, const double *__restrict__ J,
+                                             long t, const double (&mm)[D][D]) {
+  double iJ, rho, v[D], T;
+  node_prim<D>(G, JU, J, t, iJ, rho, v, T);
+  return cfl_rate_prim<D>(G, iJ, rho, v, T, mm);
 }
 
 template <int D>
