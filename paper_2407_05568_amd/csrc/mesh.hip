@@ -418,6 +418,8 @@ __global__ void __launch_bounds__(256) k_filter_multi2(Geo G, const double *__re
 template <int D>
 __global__ void k_sor(Geo G, const double *__restrict__ omega, double *__restrict__ x, int colour, double relax,
                       double *part) {
+  // no contraction: k_sor_multi2 repeats this arithmetic and must give the same bits
+#pragma clang fp contract(off)
   const int t = blockIdx.x * blockDim.x + threadIdx.x, i1 = blockIdx.y * blockDim.y + threadIdx.y,
             i2 = blockIdx.z;
   const int i0 = 2 * t + ((i1 + i2 + colour) & 1);
@@ -459,6 +461,97 @@ __global__ void k_sor(Geo G, const double *__restrict__ omega, double *__restric
       r = fmax(r, fabs(v - old));
       x[(long)j * G.N + q] = old + relax * (v - old);
     }
+  }
+  if (part) {
+    double mr = block_max(r);
+    if (flat_tid() == 0) part[flat_bid()] = mr;
+  }
+}
+
+// ---- several red-black SOR sweeps per launch (2D, outflow in both directions) ----------------
+// A block of 32 x 8 threads owns a JS_X x JS_Y tile and loads it with omega and a halo of
+// h = 2 nsw nodes into LDS (nsw <= JS_S sweeps).  Half-sweep q (colour q mod 2, colour 0 first as
+// in k_sor) updates its colour in place over the extended region shrunk by q, reading the other
+// colour, so the owned tile is exact after the 2 nsw half-sweeps; a thread takes the two columns
+// 2 tx and 2 tx + 1 of its rows and updates the one of the current colour, so every lane works in
+// every half-sweep.  A node next to a wall takes the self terms of k_sor instead of a ghost, so no
+// ghost values are needed; the per-node arithmetic is k_sor's, term for term and with contraction
+// off in both, so nsw sweeps here equal nsw sweeps of k_sor bit for bit.  part != nullptr: the
+// partial maxima of |v - x| over the last sweep's two half-sweeps.  The global arrays alternate
+// (xin is never written): other blocks read xin's values around their tiles.
+constexpr int JS_X = 56, JS_Y = 12, JS_S = 2;
+constexpr int JS_EX = JS_X + 4 * JS_S, JS_EY = JS_Y + 4 * JS_S, JS_NE = JS_EX * JS_EY;
+static_assert(JS_EX <= 64, "two extended columns per thread of a 32-thread row");
+
+__global__ void __launch_bounds__(256) k_sor_multi2(Geo G, const double *__restrict__ omega,
+                                                    const double *__restrict__ xin, double *__restrict__ xout,
+                                                    int nsw, double relax, double *part) {
+#pragma clang fp contract(off)
+  __shared__ double sw[JS_NE], sx[2][JS_NE];
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 32 + tx;
+  const int hw = 2 * nsw, exn = JS_X + 2 * hw, eyn = JS_Y + 2 * hw, nex = exn * eyn;
+  const int gx0 = blockIdx.x * JS_X - hw, gy0 = blockIdx.y * JS_Y - hw;
+  const int n0 = G.n[0], n1 = G.n[1];
+  for (int e = tid; e < nex; e += 256) {
+    const int gx = gx0 + e % exn, gy = gy0 + e / exn;
+    const bool in = gx >= 0 && gx < n0 && gy >= 0 && gy < n1;
+    const long t = in ? lin(G, gx, gy, 0) : 0;
+    sw[e] = in ? omega[t] : 0.0;
+    sx[0][e] = in ? xin[t] : 0.0;
+    sx[1][e] = in ? xin[G.N + t] : 0.0;
+  }
+  __syncthreads();
+  const double h2x = G.idxi[0] * G.idxi[0], h2y = G.idxi[1] * G.idxi[1];
+  const double wall[2][2] = {{G.lo[0], G.hi[0]}, {G.lo[1], G.hi[1]}};
+  double r = 0.0;
+  for (int q = 1; q <= hw; ++q) {
+    const int colour = (q - 1) & 1;
+    for (int ey = ty; ey < eyn; ey += 8) {
+      const int gy = gy0 + ey;
+      const int ex = 2 * tx + ((gx0 + 2 * tx + gy + colour) & 1);  // the column of this colour
+      const int gx = gx0 + ex;
+      if (ey < q || ey >= eyn - q || ex < q || ex >= exn - q || gx < 0 || gx >= n0 || gy < 0 || gy >= n1) continue;
+      const int e = ey * exn + ex;
+      const double w0 = sw[e];
+      double den[2] = {0.0, 0.0}, num[2] = {0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const double h2 = k == 0 ? h2x : h2y;
+        const int step = k == 0 ? 1 : exn, ik = k == 0 ? gx : gy, nk = k == 0 ? n0 : n1;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          const int sg = side ? 1 : -1, en = e + sg * step;
+          const bool self = ik + sg < 0 || ik + sg >= nk;
+          const double wf = 0.5 * (w0 + (self ? w0 : sw[en])) * h2;
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            if (!self) {
+              den[j] += wf;
+              num[j] += wf * sx[j][en];
+            } else if (j == k) {
+              den[j] += 2.0 * wf;
+              num[j] += wf * 2.0 * wall[k][side];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const double old = sx[j][e];
+        const double v = num[j] / den[j];
+        if (q > hw - 2) r = fmax(r, fabs(v - old));
+        sx[j][e] = old + relax * (v - old);
+      }
+    }
+    __syncthreads();
+  }
+  for (int o = tid; o < JS_X * JS_Y; o += 256) {
+    const int ex = hw + o % JS_X, ey = hw + o / JS_X, gx = gx0 + ex, gy = gy0 + ey;
+    if (gx >= n0 || gy >= n1) continue;
+    const long t = lin(G, gx, gy, 0);
+    const int e = ey * exn + ex;
+    xout[t] = sx[0][e];
+    xout[G.N + t] = sx[1][e];
   }
   if (part) {
     double mr = block_max(r);
@@ -789,6 +882,24 @@ template <int D>
 static int sor_d(esvdw_ctx *c, const double *omega, double *x, int nsweep, double relax, double *resid_dev,
                  hipStream_t st) {
   const Geo &G = c->G;
+  if (D == 2 && G.bc[0] != ESVDW_BC_PERIODIC && G.bc[1] != ESVDW_BC_PERIODIC && G.s0 == 0 && nsweep > 0) {
+    const dim3 gm((G.n[0] + JS_X - 1) / JS_X, (G.n[1] + JS_Y - 1) / JS_Y, 1);
+    const long nbm = (long)gm.x * gm.y;  // <= npart
+    const double *a = x;
+    double *o = c->xtmp;
+    for (int done = 0; done < nsweep;) {
+      const int k = nsweep - done < JS_S ? nsweep - done : JS_S;
+      const bool last = done + k == nsweep;
+      hipLaunchKernelGGL(k_sor_multi2, gm, dim3(32, 8), 0, st, G, omega, a, o, k, relax, last ? c->part : nullptr);
+      a = o;
+      o = (o == c->xtmp) ? x : c->xtmp;
+      done += k;
+    }
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, c->part, nbm, c->scal + SC_RESID, 0);
+    if (a != x) launch_copy(a, x, 2L * G.N, st);
+    if (resid_dev) launch_copy(c->scal + SC_RESID, resid_dev, 1, st);
+    return CHK();
+  }
   dim3 b, g;
   node_grid((G.n[0] + 1) / 2, G.n[1], G.n[2], g, b);
   const long nb = (long)g.x * g.y * g.z;  // 2 nb <= 4 npart: both halves' partial maxima fit

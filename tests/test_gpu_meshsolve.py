@@ -49,6 +49,36 @@ def test_sor_sweeps_match_oracle(orc, torch_dev, dim, bc, n, relax, nsweep):
     assert ctx.status() == 0
 
 
+@pytest.mark.parametrize("n,nsweep", [([151, 37], 7), ([64, 64], 4), ([9, 200], 5)])
+def test_multi_sweep_sor_equals_single_sweeps(orc, torch_dev, n, nsweep):
+    """On 2D outflow grids mesh_sor runs up to two sweeps per launch from an LDS tile; nsweep
+    sweeps in one call must equal nsweep calls of one sweep bit for bit (the residual too), and
+    the oracle to rounding."""
+    torch = torch_dev
+    from paper_2407_05568_amd.esvdw import Context
+    p = synth.problem(2, n, bc="outflow")
+    ctx = Context(p)
+    rng = np.random.default_rng(n[0] * 7 + nsweep)
+    shape = (n[1], n[0])
+    omega = 1.0 + 3.0 * rng.random(shape)
+    x0 = synth.smooth_mesh(p, 5, amp=0.02)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    om = T(omega)
+    xa, xb = T(x0), T(x0)
+    ra = torch.zeros(1, dtype=torch.float64, device="cuda")
+    rb = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.mesh_sor(om, xa, nsweep, 1.9, ra)
+    for _ in range(nsweep):
+        ctx.mesh_sor(om, xb, 1, 1.9, rb)
+    torch.cuda.synchronize()
+    assert torch.equal(xa, xb)
+    assert float(ra.item()) == float(rb.item())
+    want, res_want = orc.Oracle(p).sor(omega, x0, nsweep, 1.9)
+    assert np.abs(xa.cpu().numpy() - want).max() < 1e-13
+    assert abs(float(ra.item()) - res_want) <= 1e-14
+    assert ctx.status() == 0
+
+
 def test_sor_rejects_odd_periodic_and_bad_relax(torch_dev):
     torch = torch_dev
     from paper_2407_05568_amd.esvdw import Context
