@@ -332,13 +332,27 @@ int esvdw_step(esvdw_ctx *c, double *JU, double *J, double *x, int moving, doubl
     if (!r) r = rk_stage(c, 2, dt_dev, JU, J, bU, bJ, x, xd, JU, J, nullptr, st);
     return r;
   }
-  // moving mesh: the three rk_stage calls, with each stage's update kernel also forming the
-  // next stage's mesh x_n + c_{s+1} dt xdot (c = 0, 1, 1/2, then 1 for x^{n+1}) instead of a
-  // separate launch; the stage-1 update overwrites the stage mesh its own node kernel has read
-  if (launch_rhs_mesh(c, JU, J, nullptr, nullptr, x, xd, 0.0, 1, 0, dt_dev, JU, J, aU, aJ, x, xd, 1.0, c->xtmp, st) ||
-      launch_rhs_mesh(c, aU, aJ, nullptr, nullptr, c->xtmp, xd, 0.0, 1, 1, dt_dev, JU, J, bU, bJ, x, xd, 0.5, c->xtmp,
+  // moving mesh: the three rk_stage calls.  In 2D the node kernel forms each stage's mesh
+  // x_n + c_s dt xdot (c = 0, 1, 1/2) itself, at the source nodes with the update kernel's
+  // arithmetic; elsewhere each stage's update kernel forms the next stage's mesh instead of a
+  // separate launch (the stage-1 update overwrites the stage mesh its own node kernel has read).
+  // The stage-2 update forms x^{n+1} = x_n + dt xdot in place.
+  if (c->G.dim == 2) {
+    if (launch_rhs_mesh(c, JU, J, nullptr, nullptr, x, xd, 0.0, 0.0, 1, 0, dt_dev, JU, J, aU, aJ, nullptr, nullptr,
+                        0.0, nullptr, st) ||
+        launch_rhs_mesh(c, aU, aJ, nullptr, nullptr, x, xd, 0.0, 1.0, 1, 1, dt_dev, JU, J, bU, bJ, nullptr, nullptr,
+                        0.0, nullptr, st) ||
+        launch_rhs_mesh(c, bU, bJ, nullptr, nullptr, x, xd, 0.0, 0.5, 1, 2, dt_dev, JU, J, JU, J, x, xd, 1.0, x, st) ||
+        launch_step_fill_mesh(c->G, x, st))
+      return ESVDW_EHIP;
+    return ESVDW_OK;
+  }
+  if (launch_rhs_mesh(c, JU, J, nullptr, nullptr, x, xd, 0.0, 0.0, 1, 0, dt_dev, JU, J, aU, aJ, x, xd, 1.0, c->xtmp,
                       st) ||
-      launch_rhs_mesh(c, bU, bJ, nullptr, nullptr, c->xtmp, xd, 0.0, 1, 2, dt_dev, JU, J, JU, J, x, xd, 1.0, x, st) ||
+      launch_rhs_mesh(c, aU, aJ, nullptr, nullptr, c->xtmp, xd, 0.0, 0.0, 1, 1, dt_dev, JU, J, bU, bJ, x, xd, 0.5,
+                      c->xtmp, st) ||
+      launch_rhs_mesh(c, bU, bJ, nullptr, nullptr, c->xtmp, xd, 0.0, 0.0, 1, 2, dt_dev, JU, J, JU, J, x, xd, 1.0, x,
+                      st) ||
       launch_step_fill_mesh(c->G, x, st))
     return ESVDW_EHIP;
   return ESVDW_OK;

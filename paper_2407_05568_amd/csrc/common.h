@@ -147,6 +147,38 @@ __device__ __forceinline__ double stage_x(const Geo &G, const double *__restrict
   return v;
 }
 
+// The stage mesh xn + cdt xd (cdt = c_s dt) at any index within the ghost reach, formed at the
+// interior source node with the arithmetic of the update kernels' next-stage mesh and then mapped
+// as mesh_at maps a coordinate: the same bits as that materialised mesh read through mesh_at.
+__device__ __forceinline__ double stage_x_src(const Geo &G, const double *__restrict__ xn,
+                                              const double *__restrict__ xd, double cs, double dt, int j, int i0,
+                                              int i1, int i2) {
+  int ii[3] = {i0, i1, i2};
+  double sg = 1.0, off = 0.0;
+  bool ghost = false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (k >= G.dim) break;
+    int i = ii[k], n = G.n[k];
+    if (i >= 0 && i < n) continue;
+    ghost = true;
+    if (G.bc[k] == ESVDW_BC_PERIODIC) {
+      int q = floordiv(i, n);
+      ii[k] = i - q * n;
+      if (k == j) off = q * G.period[k];
+    } else {
+      ii[k] = i < 0 ? -1 - i : 2 * n - 1 - i;
+      if (k == j) {
+        sg = -1.0;
+        off = 2.0 * (i < 0 ? G.lo[k] : G.hi[k]);
+      }
+    }
+  }
+  const long q = (long)j * G.N + lin(G, ii[0], ii[1], ii[2]);
+  const double v = xn[q] + cs * dt * xd[q];
+  return ghost ? sg * v + off : v;
+}
+
 // delta_k[x_j] at (i0, i1, i2): (1/2) sum_m alpha_m (x_{i+m e_k} - x_{i-m e_k})
 __device__ __forceinline__ double delta_x(const Geo &G, const double *xn, const double *xd, double cdt, int k, int j,
                                           int i0, int i1, int i2) {
@@ -279,6 +311,21 @@ __device__ __forceinline__ void mesh_tile_fill(const Geo &G, const double *__res
     const bool in = i0 >= -6 && i0 < G.n[0] + 6 && i1 >= -6 && i1 < G.n[1] + 6;
     T.x[0][b][a] = in ? stage_x(G, xn, xd, cdt, 0, i0, i1, 0) : 0.0;
     T.x[1][b][a] = in ? stage_x(G, xn, xd, cdt, 1, i0, i1, 0) : 0.0;
+  }
+}
+
+// the same tile of the stage mesh xn + cs dt xd formed at the source nodes (stage_x_src)
+template <int TX, int TY>
+__device__ __forceinline__ void mesh_tile_fill_stage(const Geo &G, const double *__restrict__ xn,
+                                                     const double *__restrict__ xd, double cs, double dt, int c0,
+                                                     int c1, MeshTile2<TX, TY> &T, int tid, int nth) {
+  constexpr int W = TX + 6, NS = W * (TY + 6);
+  for (int idx = tid; idx < NS; idx += nth) {
+    const int a = idx % W, b = idx / W;
+    const int i0 = c0 - 3 + a, i1 = c1 - 3 + b;
+    const bool in = i0 >= -6 && i0 < G.n[0] + 6 && i1 >= -6 && i1 < G.n[1] + 6;
+    T.x[0][b][a] = in ? stage_x_src(G, xn, xd, cs, dt, 0, i0, i1, 0) : 0.0;
+    T.x[1][b][a] = in ? stage_x_src(G, xn, xd, cs, dt, 1, i0, i1, 0) : 0.0;
   }
 }
 

@@ -13,7 +13,7 @@ int launch_rhs(esvdw_ctx *c, const double *JU, const double *J, const double *me
                const double *bJU, const double *bJ, double *oJU, double *oJ, hipStream_t st);
 // launch_rhs whose update kernel also writes the next stage's mesh mout = mx + mf dt mxd per node
 int launch_rhs_mesh(esvdw_ctx *c, const double *JU, const double *J, const double *met, const double *xit,
-                    const double *xn, const double *xd, double cdt, int mode, int s, const double *dtp,
+                    const double *xn, const double *xd, double cdt, double cs, int mode, int s, const double *dtp,
                     const double *bJU, const double *bJ, double *oJU, double *oJ, const double *mx, const double *mxd,
                     double mf, double *mout, hipStream_t st);
 int launch_uniform_mesh(esvdw_ctx *c, double *x, hipStream_t st);

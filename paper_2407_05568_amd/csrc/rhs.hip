@@ -169,14 +169,21 @@ __global__ void k_nodes(Geo G, const double *__restrict__ JU, const double *__re
 // are in flight together (measured: 64 x 16 with the row loop rolled took 10 us more per launch).
 #define ND_TX 64
 #define ND_TY 8
+// cs != 0 (with xd and dtp): the stage mesh is xn + cs dt xd, formed here at the source nodes
+// with the arithmetic of the update kernels' next-stage mesh (the same bits as that mesh)
 __global__ void __launch_bounds__(256) k_nodes_t2(Geo G, const double *__restrict__ JU, const double *__restrict__ J,
                                                   const double *__restrict__ xn, const double *__restrict__ xd,
-                                                  double cdt, double *__restrict__ nd, unsigned *flags) {
+                                                  double cdt, const double *__restrict__ dtp, double cs,
+                                                  double *__restrict__ nd, unsigned *flags) {
   __shared__ MeshTile2<ND_TX, ND_TY> T;
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int b0 = blockIdx.x * ND_TX, b1 = blockIdx.y * ND_TY;  // first padded node of the tile
-  const double *xv_src = (xd && cdt != 0.0) ? xd : nullptr;
-  mesh_tile_fill<ND_TX, ND_TY>(G, xn, xv_src, cdt, b0 - G.g[0], b1 - G.g[1], T, ty * 64 + tx, 256);
+  if (cs != 0.0 && xd && dtp) {
+    mesh_tile_fill_stage<ND_TX, ND_TY>(G, xn, xd, cs, *dtp, b0 - G.g[0], b1 - G.g[1], T, ty * 64 + tx, 256);
+  } else {
+    const double *xv_src = (xd && cdt != 0.0) ? xd : nullptr;
+    mesh_tile_fill<ND_TX, ND_TY>(G, xn, xv_src, cdt, b0 - G.g[0], b1 - G.g[1], T, ty * 64 + tx, 256);
+  }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < ND_TY / 4; ++r) {
@@ -392,9 +399,9 @@ template <int D> static void launch_flux_d(esvdw_ctx *c, int K, hipStream_t st) 
 
 template <int D>
 static int rhs_pipeline_d(esvdw_ctx *c, const double *JU, const double *J, const double *met, const double *xit,
-                          const double *xn, const double *xd, double cdt, int mode, int s, const double *dtp,
-                          const double *bJU, const double *bJ, double *oJU, double *oJ, const double *mx,
-                          const double *mxd, double mf, double *mout, hipStream_t st) {
+                          const double *xn, const double *xd, double cdt, double cs, int mode, int s,
+                          const double *dtp, const double *bJU, const double *bJ, double *oJU, double *oJ,
+                          const double *mx, const double *mxd, double mf, double *mout, hipStream_t st) {
   const Geo &G = c->G;
   if (!met && D == 3)
     if (launch_dprod(c, xn, xd, cdt, st)) return -1;
@@ -403,7 +410,7 @@ static int rhs_pipeline_d(esvdw_ctx *c, const double *JU, const double *J, const
   node_grid(G.n[0], G.n[1], G.n[2], gu, bu);
   if (D == 2 && !met) {
     dim3 gt((G.E0 + ND_TX - 1) / ND_TX, (G.P[1] + ND_TY - 1) / ND_TY, 1);
-    hipLaunchKernelGGL(k_nodes_t2, gt, dim3(64, 4, 1), 0, st, G, JU, J, xn, xd, cdt, c->node, c->flags);
+    hipLaunchKernelGGL(k_nodes_t2, gt, dim3(64, 4, 1), 0, st, G, JU, J, xn, xd, cdt, dtp, cs, c->node, c->flags);
   } else {
     hipLaunchKernelGGL(k_nodes<D>, gn, bn, 0, st, G, JU, J, met, xit, xn, xd, cdt, c->dprod, c->dpN, c->node,
                        c->flags);
@@ -432,20 +439,23 @@ static int rhs_pipeline_d(esvdw_ctx *c, const double *JU, const double *J, const
 }
 
 int launch_rhs_mesh(esvdw_ctx *c, const double *JU, const double *J, const double *met, const double *xit,
-                    const double *xn, const double *xd, double cdt, int mode, int s, const double *dtp,
+                    const double *xn, const double *xd, double cdt, double cs, int mode, int s, const double *dtp,
                     const double *bJU, const double *bJ, double *oJU, double *oJ, const double *mx, const double *mxd,
                     double mf, double *mout, hipStream_t st) {
   switch (c->G.dim) {
-    case 1: return rhs_pipeline_d<1>(c, JU, J, met, xit, xn, xd, cdt, mode, s, dtp, bJU, bJ, oJU, oJ, mx, mxd, mf, mout, st);
-    case 2: return rhs_pipeline_d<2>(c, JU, J, met, xit, xn, xd, cdt, mode, s, dtp, bJU, bJ, oJU, oJ, mx, mxd, mf, mout, st);
-    default: return rhs_pipeline_d<3>(c, JU, J, met, xit, xn, xd, cdt, mode, s, dtp, bJU, bJ, oJU, oJ, mx, mxd, mf, mout, st);
+    case 1:
+      return rhs_pipeline_d<1>(c, JU, J, met, xit, xn, xd, cdt, cs, mode, s, dtp, bJU, bJ, oJU, oJ, mx, mxd, mf, mout, st);
+    case 2:
+      return rhs_pipeline_d<2>(c, JU, J, met, xit, xn, xd, cdt, cs, mode, s, dtp, bJU, bJ, oJU, oJ, mx, mxd, mf, mout, st);
+    default:
+      return rhs_pipeline_d<3>(c, JU, J, met, xit, xn, xd, cdt, cs, mode, s, dtp, bJU, bJ, oJU, oJ, mx, mxd, mf, mout, st);
   }
 }
 
 int launch_rhs(esvdw_ctx *c, const double *JU, const double *J, const double *met, const double *xit,
                const double *xn, const double *xd, double cdt, int mode, int s, const double *dtp,
                const double *bJU, const double *bJ, double *oJU, double *oJ, hipStream_t st) {
-  return launch_rhs_mesh(c, JU, J, met, xit, xn, xd, cdt, mode, s, dtp, bJU, bJ, oJU, oJ, nullptr, nullptr, 0.0,
+  return launch_rhs_mesh(c, JU, J, met, xit, xn, xd, cdt, 0.0, mode, s, dtp, bJU, bJ, oJU, oJ, nullptr, nullptr, 0.0,
                          nullptr, st);
 }
 
