@@ -273,6 +273,56 @@ __global__ void __launch_bounds__(256, 3)
   update_combine<2>(G, L, t, mode, s, dtp, base_JU, base_J, in_JU, in_J, out_JU, out_J, flags);
 }
 
+// 3D: the direction-0 interface fluxes of a 62 x 4 x 1 tile and the update of the 61 x 4 nodes
+// between them, as k_flux_upd2 does in 2D; the direction-1 and direction-2 fluxes are read from
+// their buffers.  The node's sums are those of update_point (direction 0, then 1, then 2).
+__global__ void __launch_bounds__(256, 3)
+    k_flux_upd3(Geo G, const double *__restrict__ nd, const double *__restrict__ F1, long nif1,
+                const double *__restrict__ F2, long nif2, int mode, int s, const double *__restrict__ dtp,
+                const double *__restrict__ base_JU, const double *__restrict__ base_J,
+                const double *__restrict__ in_JU, const double *__restrict__ in_J, double *__restrict__ out_JU,
+                double *__restrict__ out_J, unsigned *flags, const double *mx, const double *mxd, double mf,
+                double *mout) {
+  constexpr int NV = 5;
+  __shared__ double sP[FluxLds<3, 0, FU_TX, FU_TY, 1>::SIZE];
+  static_assert(FluxLds<3, 0, FU_TX, FU_TY, 1>::SIZE >= (NV + 1) * 256, "the interface fluxes reuse the pair-flux LDS");
+  const int bx0 = blockIdx.x * (FU_TX - 1), by0 = blockIdx.y * FU_TY, i2 = blockIdx.z;
+  double Fl[NV + 1];
+  int a0, a1, a2;
+  const bool ok =
+      flux_tile_eval<3, 0, FU_TX, FU_TY, 1, FU_PX, FU_TY, false>(G, nd, flags, bx0, by0, i2, sP, Fl, a0, a1, a2);
+  __syncthreads();  // every thread has read its pair fluxes
+  const int tid = threadIdx.x, tx = tid % FU_PX, ty = tid / FU_PX;
+  if (ok) {
+#pragma unroll
+    for (int c = 0; c <= NV; ++c) sP[c * 256 + tid] = Fl[c];
+  }
+  __syncthreads();
+  const int i0 = bx0 + tx, i1 = by0 + ty;
+  if (tx >= FU_TX - 1 || i0 >= G.n[0] || i1 >= G.n[1]) return;
+  const long t = lin(G, i0, i1, i2);
+  if (mout) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) mout[(long)j * G.N + t] = mx[(long)j * G.N + t] + mf * (*dtp) * mxd[(long)j * G.N + t];
+  }
+  double L[NV + 1];
+#pragma unroll
+  for (int c = 0; c <= NV; ++c) L[c] = 0.0;
+#pragma unroll
+  for (int c = 0; c <= NV; ++c) L[c] += (sP[c * 256 + tid] - sP[c * 256 + tid + 1]) * G.idxi[0];
+  {
+    const long r = ((long)i2 * (G.n[1] + 1) + i1) * G.n[0] + i0;
+#pragma unroll
+    for (int c = 0; c <= NV; ++c) L[c] += (F1[(long)c * nif1 + r] - F1[(long)c * nif1 + r + G.n[0]]) * G.idxi[1];
+  }
+  {
+    const long r = ((long)i2 * G.n[1] + i1) * G.n[0] + i0, st = (long)G.n[0] * G.n[1];
+#pragma unroll
+    for (int c = 0; c <= NV; ++c) L[c] += (F2[(long)c * nif2 + r] - F2[(long)c * nif2 + r + st]) * G.idxi[2];
+  }
+  update_combine<3>(G, L, t, mode, s, dtp, base_JU, base_J, in_JU, in_J, out_JU, out_J, flags);
+}
+
 // backward-facing step: the state at the solid nodes next to the step becomes the image of its
 // fluid source (normal momentum reversed, J copied); the corner block takes the image across
 // the vertical face.  One thread per node of the solid block; sources are fluid nodes.
@@ -429,9 +479,17 @@ static int rhs_pipeline_d(esvdw_ctx *c, const double *JU, const double *J, const
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
   }
+  if (D == 3) {
+    // directions 1 and 2 first; the direction-0 flux kernel then also forms the update
+    launch_flux_d<D>(c, 1, st);
+    launch_flux_d<D>(c, 2, st);
+    dim3 gf((G.n[0] + FU_TX - 2) / (FU_TX - 1), (G.n[1] + FU_TY - 1) / FU_TY, G.n[2]);
+    hipLaunchKernelGGL(k_flux_upd3, gf, dim3(256), 0, st, G, c->node, c->flux[1], c->nif[1], c->flux[2], c->nif[2],
+                       mode, s, dtp, bJU, bJ, JU, J, oJU, oJ, c->flags, mx, mxd, mf, mout);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  }
   launch_flux_d<D>(c, 0, st);
   if (D > 1) launch_flux_d<D>(c, 1, st);
-  if (D > 2) launch_flux_d<D>(c, 2, st);
   hipLaunchKernelGGL(k_update<D>, gu, bu, 0, st, G, c->flux[0], c->flux[1], c->flux[2],
                      c->nif[0], c->nif[1], c->nif[2], mode, s, dtp, bJU, bJ, JU, J, oJU, oJ, c->flags, mx, mxd, mf,
                      mout);
