@@ -175,7 +175,7 @@ __device__ __forceinline__ double stage_x_src(const Geo &G, const double *__rest
     }
   }
   const long q = (long)j * G.N + lin(G, ii[0], ii[1], ii[2]);
-  const double v = xn[q] + cs * dt * xd[q];
+  const double v = fma(cs * dt, xd[q], xn[q]);
   return ghost ? sg * v + off : v;
 }
 

@@ -240,21 +240,44 @@ __global__ void __launch_bounds__(256, 3)
   double Fl[5];
   int a0, a1, a2;
   const bool ok = flux_tile_eval<2, 0, FU_TX, FU_TY, 1, FU_PX, FU_TY, ST>(G, nd, flags, bx0, by0, 0, sP, Fl, a0, a1, a2);
-  __syncthreads();  // every thread has read its pair fluxes
   const int tid = threadIdx.x, tx = tid % FU_PX, ty = tid / FU_PX;
+  const int i0 = bx0 + tx, i1 = by0 + ty;
+  const bool upd = tx < FU_TX - 1 && i0 < G.n[0] && i1 < G.n[1];
+  const long t = (long)i1 * G.n[0] + i0;
+  const bool solid = ST && upd && step_solid(G, i0, i1);
+  // the update's operands are loaded before the two barriers below, so that their latency
+  // overlaps the waits (the direction-0 fluxes of the tile are not yet in LDS)
+  double f1l[5], f1h[5], mxv[2], mxdv[2];
+  const double dtm = mout ? *dtp : 0.0;
+  UpdIn<2> u;
+  u.dt = mode == 1 ? *dtp : 0.0;
+  if (upd && !solid) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      f1l[c] = F1[(long)c * nif1 + t];
+      f1h[c] = F1[(long)c * nif1 + t + G.n[0]];
+    }
+    update_load<2>(G, t, mode, s, base_JU, base_J, in_JU, in_J, u);
+  }
+  if (upd && mout) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      mxv[j] = mx[(long)j * G.N + t];
+      mxdv[j] = mxd[(long)j * G.N + t];
+    }
+  }
+  __syncthreads();  // every thread has read its pair fluxes
   if (ok) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) sP[c * 256 + tid] = Fl[c];
   }
   __syncthreads();
-  const int i0 = bx0 + tx, i1 = by0 + ty;
-  if (tx >= FU_TX - 1 || i0 >= G.n[0] || i1 >= G.n[1]) return;
-  const long t = (long)i1 * G.n[0] + i0;
+  if (!upd) return;
   if (mout) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) mout[(long)j * G.N + t] = mx[(long)j * G.N + t] + mf * (*dtp) * mxd[(long)j * G.N + t];
+    for (int j = 0; j < 2; ++j) mout[(long)j * G.N + t] = fma(mf * dtm, mxdv[j], mxv[j]);
   }
-  if (ST && step_solid(G, i0, i1)) {
+  if (solid) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) out_JU[(long)c * G.N + t] = mode == 1 ? base_JU[(long)c * G.N + t] : 0.0;
     out_J[t] = mode == 1 ? base_J[t] : 0.0;
@@ -265,12 +288,9 @@ __global__ void __launch_bounds__(256, 3)
   for (int c = 0; c < 5; ++c) L[c] = 0.0;
 #pragma unroll
   for (int c = 0; c < 5; ++c) L[c] += (sP[c * 256 + tid] - sP[c * 256 + tid + 1]) * G.idxi[0];
-  {
-    const long r = (long)i1 * G.n[0] + i0;
 #pragma unroll
-    for (int c = 0; c < 5; ++c) L[c] += (F1[(long)c * nif1 + r] - F1[(long)c * nif1 + r + G.n[0]]) * G.idxi[1];
-  }
-  update_combine<2>(G, L, t, mode, s, dtp, base_JU, base_J, in_JU, in_J, out_JU, out_J, flags);
+  for (int c = 0; c < 5; ++c) L[c] += (f1l[c] - f1h[c]) * G.idxi[1];
+  update_store<2>(G, L, u, t, mode, s, out_JU, out_J, flags);
 }
 
 // 3D: the direction-0 interface fluxes of a 62 x 4 x 1 tile and the update of the 61 x 4 nodes
@@ -291,36 +311,55 @@ __global__ void __launch_bounds__(256, 3)
   int a0, a1, a2;
   const bool ok =
       flux_tile_eval<3, 0, FU_TX, FU_TY, 1, FU_PX, FU_TY, false>(G, nd, flags, bx0, by0, i2, sP, Fl, a0, a1, a2);
-  __syncthreads();  // every thread has read its pair fluxes
   const int tid = threadIdx.x, tx = tid % FU_PX, ty = tid / FU_PX;
+  const int i0 = bx0 + tx, i1 = by0 + ty;
+  const bool upd = tx < FU_TX - 1 && i0 < G.n[0] && i1 < G.n[1];
+  const long t = lin(G, i0, i1, i2);
+  // the update's operands are loaded before the two barriers below (as in k_flux_upd2)
+  double f1l[NV + 1], f1h[NV + 1], f2l[NV + 1], f2h[NV + 1], mxv[3], mxdv[3];
+  const double dtm = mout ? *dtp : 0.0;
+  UpdIn<3> u;
+  u.dt = mode == 1 ? *dtp : 0.0;
+  if (upd) {
+    const long r1 = ((long)i2 * (G.n[1] + 1) + i1) * G.n[0] + i0;
+    const long r2 = ((long)i2 * G.n[1] + i1) * G.n[0] + i0, st = (long)G.n[0] * G.n[1];
+#pragma unroll
+    for (int c = 0; c <= NV; ++c) {
+      f1l[c] = F1[(long)c * nif1 + r1];
+      f1h[c] = F1[(long)c * nif1 + r1 + G.n[0]];
+      f2l[c] = F2[(long)c * nif2 + r2];
+      f2h[c] = F2[(long)c * nif2 + r2 + st];
+    }
+    update_load<3>(G, t, mode, s, base_JU, base_J, in_JU, in_J, u);
+    if (mout) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        mxv[j] = mx[(long)j * G.N + t];
+        mxdv[j] = mxd[(long)j * G.N + t];
+      }
+    }
+  }
+  __syncthreads();  // every thread has read its pair fluxes
   if (ok) {
 #pragma unroll
     for (int c = 0; c <= NV; ++c) sP[c * 256 + tid] = Fl[c];
   }
   __syncthreads();
-  const int i0 = bx0 + tx, i1 = by0 + ty;
-  if (tx >= FU_TX - 1 || i0 >= G.n[0] || i1 >= G.n[1]) return;
-  const long t = lin(G, i0, i1, i2);
+  if (!upd) return;
   if (mout) {
 #pragma unroll
-    for (int j = 0; j < 3; ++j) mout[(long)j * G.N + t] = mx[(long)j * G.N + t] + mf * (*dtp) * mxd[(long)j * G.N + t];
+    for (int j = 0; j < 3; ++j) mout[(long)j * G.N + t] = fma(mf * dtm, mxdv[j], mxv[j]);
   }
   double L[NV + 1];
 #pragma unroll
   for (int c = 0; c <= NV; ++c) L[c] = 0.0;
 #pragma unroll
   for (int c = 0; c <= NV; ++c) L[c] += (sP[c * 256 + tid] - sP[c * 256 + tid + 1]) * G.idxi[0];
-  {
-    const long r = ((long)i2 * (G.n[1] + 1) + i1) * G.n[0] + i0;
 #pragma unroll
-    for (int c = 0; c <= NV; ++c) L[c] += (F1[(long)c * nif1 + r] - F1[(long)c * nif1 + r + G.n[0]]) * G.idxi[1];
-  }
-  {
-    const long r = ((long)i2 * G.n[1] + i1) * G.n[0] + i0, st = (long)G.n[0] * G.n[1];
+  for (int c = 0; c <= NV; ++c) L[c] += (f1l[c] - f1h[c]) * G.idxi[1];
 #pragma unroll
-    for (int c = 0; c <= NV; ++c) L[c] += (F2[(long)c * nif2 + r] - F2[(long)c * nif2 + r + st]) * G.idxi[2];
-  }
-  update_combine<3>(G, L, t, mode, s, dtp, base_JU, base_J, in_JU, in_J, out_JU, out_J, flags);
+  for (int c = 0; c <= NV; ++c) L[c] += (f2l[c] - f2h[c]) * G.idxi[2];
+  update_store<3>(G, L, u, t, mode, s, out_JU, out_J, flags);
 }
 
 // backward-facing step: the state at the solid nodes next to the step becomes the image of its
@@ -362,7 +401,7 @@ __global__ void k_update(Geo G, const double *__restrict__ F0, const double *__r
     // the next stage's mesh x_n + f dt xdot at this node (k_axpy_mesh's arithmetic; mout may be mx)
     const long t = lin(G, i0, i1, i2);
 #pragma unroll
-    for (int j = 0; j < D; ++j) mout[(long)j * G.N + t] = mx[(long)j * G.N + t] + mf * (*dtp) * mxd[(long)j * G.N + t];
+    for (int j = 0; j < D; ++j) mout[(long)j * G.N + t] = fma(mf * (*dtp), mxd[(long)j * G.N + t], mx[(long)j * G.N + t]);
   }
 }
 
@@ -398,7 +437,7 @@ __global__ void k_axpy_mesh(long n, const double *__restrict__ x, const double *
                             const double *__restrict__ dtp, double f, double *out) {
   long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (t >= n) return;
-  out[t] = x[t] + f * (*dtp) * xd[t];
+  out[t] = fma(f * (*dtp), xd[t], x[t]);
 }
 
 // =============================== launchers =======================================

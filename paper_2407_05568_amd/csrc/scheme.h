@@ -712,14 +712,33 @@ __device__ __forceinline__ void flux_tile(const Geo &G, const double *__restrict
 
 // =============================== update ==========================================
 
-// RK-stage output at node slot t from the semi-discrete RHS L (nv + 1 values).  mode 0: write
-// dJU, dJ.  mode 1: SSP-RK3 stage s combination with dt from the device.
+// operands of the SSP-RK3 stage combination at node slot t: dt (set by the caller, the same for
+// every node), the stage input and (stages 1 and 2) the base values; loaded apart from the
+// combination so that a kernel can issue the loads early (mode 0 loads nothing)
+template <int D> struct UpdIn {
+  double yin[D + 3], yb[D + 3], dt;
+};
 template <int D>
-__device__ __forceinline__ void update_combine(const Geo &G, const double (&L)[D + 3], long t, int mode, int s,
-                                               const double *__restrict__ dtp, const double *__restrict__ base_JU,
-                                               const double *__restrict__ base_J, const double *__restrict__ in_JU,
-                                               const double *__restrict__ in_J, double *__restrict__ out_JU,
-                                               double *__restrict__ out_J, unsigned *flags) {
+__device__ __forceinline__ void update_load(const Geo &G, long t, int mode, int s, const double *__restrict__ base_JU,
+                                            const double *__restrict__ base_J, const double *__restrict__ in_JU,
+                                            const double *__restrict__ in_J, UpdIn<D> &u) {
+  constexpr int NV = D + 2;
+  if (mode != 1) return;
+#pragma unroll
+  for (int c = 0; c <= NV; ++c) {
+    const double *inp = c < NV ? in_JU + (long)c * G.N : in_J;
+    const double *bp = c < NV ? base_JU + (long)c * G.N : base_J;
+    u.yin[c] = inp[t];
+    u.yb[c] = s != 0 ? bp[t] : 0.0;
+  }
+}
+
+// RK-stage output at node slot t from the semi-discrete RHS L (nv + 1 values) and the operands
+// u.  mode 0: write dJU, dJ.  mode 1: SSP-RK3 stage s combination.
+template <int D>
+__device__ __forceinline__ void update_store(const Geo &G, const double (&L)[D + 3], const UpdIn<D> &u, long t,
+                                             int mode, int s, double *__restrict__ out_JU, double *__restrict__ out_J,
+                                             unsigned *flags) {
   constexpr int NV = D + 2;
   bool nan = false;
   if (mode == 0) {
@@ -731,22 +750,34 @@ __device__ __forceinline__ void update_combine(const Geo &G, const double (&L)[D
     out_J[t] = L[NV];
     nan |= isnan(L[NV]);
   } else {
-    double dt = *dtp;
+    // the fused multiply-adds are written out so that the rounding does not depend on which
+    // product the compiler would contract in a given kernel
 #pragma unroll
     for (int c = 0; c <= NV; ++c) {
-      const double *inp = c < NV ? in_JU + (long)c * G.N : in_J;
-      const double *bp = c < NV ? base_JU + (long)c * G.N : base_J;
-      double y = inp[t] + dt * L[c];
+      const double y = fma(u.dt, L[c], u.yin[c]);
       double o;
       if (s == 0) o = y;
-      else if (s == 1) o = 0.75 * bp[t] + 0.25 * y;
-      else o = (1.0 / 3.0) * bp[t] + (2.0 / 3.0) * y;
+      else if (s == 1) o = fma(0.25, y, 0.75 * u.yb[c]);
+      else o = fma(2.0 / 3.0, y, (1.0 / 3.0) * u.yb[c]);
       nan |= isnan(o);
       if (c < NV) out_JU[(long)c * G.N + t] = o;
       else out_J[t] = o;
     }
   }
   if (nan) raise_flag(flags, ESVDW_F_NAN);
+}
+
+// RK-stage output at node slot t from the semi-discrete RHS L, its operands loaded here
+template <int D>
+__device__ __forceinline__ void update_combine(const Geo &G, const double (&L)[D + 3], long t, int mode, int s,
+                                               const double *__restrict__ dtp, const double *__restrict__ base_JU,
+                                               const double *__restrict__ base_J, const double *__restrict__ in_JU,
+                                               const double *__restrict__ in_J, double *__restrict__ out_JU,
+                                               double *__restrict__ out_J, unsigned *flags) {
+  UpdIn<D> u;
+  u.dt = mode == 1 ? *dtp : 0.0;
+  update_load<D>(G, t, mode, s, base_JU, base_J, in_JU, in_J, u);
+  update_store<D>(G, L, u, t, mode, s, out_JU, out_J, flags);
 }
 
 // mode 0: write dJU, dJ.  mode 1: SSP-RK3 stage s combination with dt from the device.
