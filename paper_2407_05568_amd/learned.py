@@ -255,11 +255,15 @@ def compare(torch, run, P, frames, every, tag="", finisher="sor", presmooth=8, p
     tolerance three ways: plain (x^[0] = x^n), warm (features + inference + the same iteration
     from x^n + warm_dx, with `presmooth` Gauss-Seidel sweeps first for the SOR finisher), and,
     for the SOR finisher with previous=True, from the converged mesh of the step before (a
-    non-learned warm start, for reference).  finisher "sor" (red-black SOR) or "jacobi" (the
-    method's iteration).  The run advances with the method's own step between frames."""
+    non-learned warm start, for reference).  With the SOR finisher the warm start is also tried
+    clipped with the movement limiter's bound: x^n + Delta_gamma warm_dx, Delta_gamma the
+    limiter factor of the move x^n -> x^n + warm_dx (Section 4).  finisher "sor" (red-black
+    SOR) or "jacobi" (the method's iteration).  The run advances with the method's own step
+    between frames."""
     shape = tuple(reversed(run.p["n"][:2]))
     feat = torch.empty((2,) + shape, dtype=torch.float32, device="cuda")
     warm = torch.empty((2,) + shape, dtype=torch.float64, device="cuda")
+    gam = torch.zeros(1, dtype=torch.float64, device="cuda")
     sor = SorSolver(torch, run) if finisher == "sor" else None
     xprev = torch.empty_like(run.x) if (sor and previous) else None
     out = []
@@ -280,6 +284,18 @@ def compare(torch, run, P, frames, every, tag="", finisher="sor", presmooth=8, p
                    warm_ms=ms_w + ms_inf, infer_ms=ms_inf)
         line = "%sframe %d: plain %d sweeps %.1f ms (res %.1e) | warm %d sweeps %.1f ms (+%.2f ms net, res %.1e)" % (
             tag, k, sw_p, ms_p, res_p, sw_w, ms_w, ms_inf, res_w)
+        if sor is not None:  # the warm start clipped with the limiter's bound
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(run.stream)
+            sor.xc.copy_(run.x).add_(warm)
+            run.ctx.mesh_limiter(run.x, sor.xc, gam, run.stream)
+            warm.mul_(gam)
+            e1.record(run.stream)
+            torch.cuda.synchronize()
+            sw_l, res_l, ms_l = sor.solve(run.tol, warm=warm, presmooth=presmooth)
+            ms_l += ms_inf + e0.elapsed_time(e1)
+            rec.update(limited_sweeps=sw_l, limited_resid=res_l, limited_ms=ms_l, gamma=float(gam.item()))
+            line += " | limited (gamma %.3g) %d sweeps %.1f ms" % (float(gam.item()), sw_l, ms_l)
         if xprev is not None:
             sw_q, res_q, ms_q = sor.solve(run.tol, start=xprev)
             rec.update(prev_sweeps=sw_q, prev_resid=res_q, prev_ms=ms_q)
@@ -315,6 +331,7 @@ def main():
     ap.add_argument("--presmooth", type=int, default=8)
     ap.add_argument("--jacobi", action="store_true", help="also compare with the Jacobi finisher (slow)")
     ap.add_argument("--save", default=None, help="write the trained parameters (npz)")
+    ap.add_argument("--load", default=None, help="compare with these parameters (npz) instead of training")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     import torch
@@ -323,20 +340,28 @@ def main():
     p = synth.problem(2, [n, n], bc="outflow")
     seeds = [int(v) for v in args.train_seeds.split(",")]
     tests = [int(v) for v in args.test_seeds.split(",")]
-    t0 = time.time()
-    prims = [synth.quadrants_2d(p, synth.quadrant_states(p, sd)) for sd in seeds]
-    feats, tgts, gstats = generate(torch, p, prims, args.frames, args.every, 1e-10, "train ")
-    t_gen = time.time() - t0
-    ctx = Context(p)
-    dxi = torch.tensor([1.0 / n, 1.0 / n], dtype=torch.float64, device="cuda")
-    t0 = time.time()
-    P, hist = train(torch, ctx, feats, tgts, args.iters, args.batch, args.lr, seeds[0], log_every=1000)
-    torch.cuda.synchronize()
-    t_train = time.time() - t0
-    err_train = heldout_error(torch, ctx, P, feats, tgts, dxi)
-    _log("training frames: relative displacement error %.3f" % err_train)
-    del feats, tgts
-    if args.save:
+    if args.load:
+        Pl, meta = load_params(args.load)
+        if meta.get("size") != n:
+            raise ValueError("%s was trained at %s^2, not %d^2" % (args.load, meta.get("size"), n))
+        P = torch.from_numpy(Pl).cuda()
+        seeds, t_gen, t_train, hist, gstats = meta.get("train_seeds", seeds), 0.0, 0.0, [], None
+        err_train = meta.get("train_rel_err")
+    else:
+        t0 = time.time()
+        prims = [synth.quadrants_2d(p, synth.quadrant_states(p, sd)) for sd in seeds]
+        feats, tgts, gstats = generate(torch, p, prims, args.frames, args.every, 1e-10, "train ")
+        t_gen = time.time() - t0
+        ctx = Context(p)
+        dxi = torch.tensor([1.0 / n, 1.0 / n], dtype=torch.float64, device="cuda")
+        t0 = time.time()
+        P, hist = train(torch, ctx, feats, tgts, args.iters, args.batch, args.lr, seeds[0], log_every=1000)
+        torch.cuda.synchronize()
+        t_train = time.time() - t0
+        err_train = heldout_error(torch, ctx, P, feats, tgts, dxi)
+        _log("training frames: relative displacement error %.3f" % err_train)
+        del feats, tgts
+    if args.save and not args.load:
         save_params(args.save, P, dict(size=n, train_seeds=seeds, frames=args.frames, every=args.every,
                                        iters=args.iters, batch=args.batch, lr=args.lr, train_rel_err=err_train,
                                        command="python -m paper_2407_05568_amd.learned --size %d --iters %d --save PATH" % (n, args.iters)))
@@ -358,6 +383,10 @@ def main():
             qs = sum(r["prev_ms"] for r in recs)
             res.update(previous_ms=qs, previous_speedup=ps / qs if qs > 0 else None,
                        previous_sweeps=sum(r["prev_sweeps"] for r in recs))
+            ls = sum(r["limited_ms"] for r in recs)
+            res.update(limited_ms=ls, limited_speedup=ps / ls if ls > 0 else None,
+                       limited_sweeps=sum(r["limited_sweeps"] for r in recs),
+                       gammas=[r["gamma"] for r in recs])
         out[fin] = res
     line = json.dumps(out)
     print(line, flush=True)
