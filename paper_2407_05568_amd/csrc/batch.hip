@@ -63,8 +63,8 @@ struct esvdw_batch {
   std::vector<long> off;  // ninst + 1
   std::vector<BInst> inst;
   BInst *dI;
-  BItem *dNode, *dFlux, *dUpd;
-  int nNode, nFlux, nUpd;
+  BItem *dNode, *dFlux, *dUpd, *dFU;  // dFU: direction-0 flux + update tiles of the phased mode
+  int nNode, nFlux, nUpd, nFU;
   double *nd_pool, *f_pool, *sAU, *sAJ, *sBU, *sBJ, *cpart;
   unsigned *bar, *flags;
   // mesh redistribution (fixed sweep count, shared by all instances)
@@ -257,6 +257,25 @@ __global__ void __launch_bounds__(256, OCC) k_bph_flux(const BInst *__restrict__
   flux_item<X0, Y0, X1, Y1>(I[w.inst], w, flags, sP);
 }
 
+// the direction-0 fluxes of a 62 x 4 tile and the stage update of its 61 x 4 nodes (as the
+// single-problem k_flux_upd2), with x^{n+1} = x^n + dt xdot at stage 2 with a mesh velocity
+__global__ void __launch_bounds__(256, 3) k_bph_fupd(const BInst *__restrict__ I, const BItem *__restrict__ ifu,
+                                                     int nfu, int s, const double *__restrict__ bU,
+                                                     const double *__restrict__ bJ, const double *__restrict__ inU,
+                                                     const double *__restrict__ inJ, double *outU, double *outJ,
+                                                     double *x, const double *__restrict__ xd,
+                                                     const double *__restrict__ dt, unsigned *flags) {
+  __shared__ double sP[FluxLds<2, 0, FU_TX, FU_TY, 1>::SIZE];
+  const int it = xcd_item(nfu);
+  if (it < 0) return;
+  const BItem w = ifu[it];
+  const BInst &B = I[w.inst];
+  double *mx = (s == 2 && xd) ? x + 2 * B.off : nullptr;
+  flux_upd2_tile<false>(B.G, B.nd, B.F1, B.nif1, 1, s, dt + w.inst, bU + 4 * B.off, bJ + B.off, inU + 4 * B.off,
+                        inJ + B.off, outU + 4 * B.off, outJ + B.off, flags, mx, mx ? xd + 2 * B.off : nullptr, 1.0,
+                        mx, w.x0, w.y0, sP);
+}
+
 __global__ void __launch_bounds__(256) k_bph_update(const BInst *__restrict__ I, const BItem *__restrict__ iupd,
                                                     int nupd, int s, const double *__restrict__ bU,
                                                     const double *__restrict__ bJ, const double *__restrict__ inU,
@@ -439,10 +458,11 @@ static int launch_phased_v(esvdw_batch *b, int s, const double *bU, const double
   }
   hipLaunchKernelGGL(k_bph_nodes, dim3(xcd_grid(b->nNode)), dim3(256), 0, st, b->dI, b->dNode, b->nNode, s, inU, inJ,
                      x, xd, dt, b->flags);
+  // the flux list holds the direction-1 tiles; the direction-0 tiles form the update
   hipLaunchKernelGGL((k_bph_flux<C::X0, C::Y0, C::X1, C::Y1, C::OCC>), dim3(xcd_grid(b->nFlux)), dim3(256), 0, st,
                      b->dI, b->dFlux, b->nFlux, b->flags);
-  hipLaunchKernelGGL(k_bph_update, dim3(xcd_grid(b->nUpd)), dim3(256), 0, st, b->dI, b->dUpd, b->nUpd, s, bU, bJ,
-                     inU, inJ, outU, outJ, x, xd, dt, b->flags);
+  hipLaunchKernelGGL(k_bph_fupd, dim3(xcd_grid(b->nFU)), dim3(256), 0, st, b->dI, b->dFU, b->nFU, s, bU, bJ, inU, inJ,
+                     outU, outJ, x, xd, dt, b->flags);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -463,32 +483,49 @@ static int launch_stage(esvdw_batch *b, int s, const double *bU, const double *b
   }
 }
 
-template <int V> static void flux_items(const esvdw_batch *b, std::vector<BItem> &v) {
+// flux tiles of tile set V: both directions, or (dir0 false) direction 1 only
+template <int V> static void flux_items(const esvdw_batch *b, std::vector<BItem> &v, bool dir0) {
   using C = BVar<V>;
   v.clear();
   for (int i = 0; i < b->ninst; ++i) {
     const Geo &G = b->geo[i];
-    for (int y = 0; y < G.n[1]; y += C::Y0)
-      for (int x = 0; x < G.n[0] + 1; x += C::X0) v.push_back({i, x, y, 0});
+    if (dir0)
+      for (int y = 0; y < G.n[1]; y += C::Y0)
+        for (int x = 0; x < G.n[0] + 1; x += C::X0) v.push_back({i, x, y, 0});
     for (int y = 0; y < G.n[1] + 1; y += C::Y1)
       for (int x = 0; x < G.n[0]; x += C::X1) v.push_back({i, x, y, 1});
   }
 }
 
+// a device copy of a work list (replacing *d)
+static int upload_items(BItem **d, int *n, const std::vector<BItem> &items) {
+  if (*d) (void)hipFree(*d);
+  *d = nullptr;
+  *n = 0;
+  if (items.empty()) return 1;
+  if (!HIPOK(hipMalloc((void **)d, items.size() * sizeof(BItem)))) return 0;
+  if (!HIPOK(hipMemcpy(*d, items.data(), items.size() * sizeof(BItem), hipMemcpyHostToDevice))) return 0;
+  *n = (int)items.size();
+  return 1;
+}
+
 static int set_flux_items(esvdw_batch *b, int v) {
-  std::vector<BItem> items;
+  std::vector<BItem> items, fu;
+  const bool phased = v >= BATCH_NTILE;  // the phased mode fuses the direction-0 fluxes into the update
   switch (v % BATCH_NTILE) {
-    case 0: flux_items<0>(b, items); break;
-    case 1: flux_items<1>(b, items); break;
-    case 2: flux_items<2>(b, items); break;
-    case 3: flux_items<3>(b, items); break;
-    default: flux_items<4>(b, items); break;
+    case 0: flux_items<0>(b, items, !phased); break;
+    case 1: flux_items<1>(b, items, !phased); break;
+    case 2: flux_items<2>(b, items, !phased); break;
+    case 3: flux_items<3>(b, items, !phased); break;
+    default: flux_items<4>(b, items, !phased); break;
   }
-  if (b->dFlux) (void)hipFree(b->dFlux);
-  b->dFlux = nullptr;
-  if (!HIPOK(hipMalloc((void **)&b->dFlux, items.size() * sizeof(BItem)))) return 0;
-  if (!HIPOK(hipMemcpy(b->dFlux, items.data(), items.size() * sizeof(BItem), hipMemcpyHostToDevice))) return 0;
-  b->nFlux = (int)items.size();
+  if (phased)
+    for (int i = 0; i < b->ninst; ++i) {  // tiles of FU_TX interfaces stepping by FU_TX - 1 nodes
+      const Geo &G = b->geo[i];
+      for (int y = 0; y < G.n[1]; y += FU_TY)
+        for (int x = 0; x < G.n[0]; x += FU_TX - 1) fu.push_back({i, x, y, 0});
+    }
+  if (!upload_items(&b->dFlux, &b->nFlux, items) || !upload_items(&b->dFU, &b->nFU, fu)) return 0;
   b->variant = v;
   return 1;
 }
@@ -502,7 +539,7 @@ extern "C" {
 
 void esvdw_batch_destroy(esvdw_batch *b) {
   if (!b) return;
-  void *bufs[] = {b->dI,  b->dNode, b->dFlux, b->dUpd, b->nd_pool, b->f_pool, b->sAU,  b->sAJ,
+  void *bufs[] = {b->dI,  b->dNode, b->dFlux, b->dUpd, b->dFU, b->nd_pool, b->f_pool, b->sAU,  b->sAJ,
                   b->sBU, b->sBJ,   b->cpart, b->bar,  b->flags,   b->rg,     b->term, b->omA,
                   b->omB, b->xa,    b->xb,    b->part3, b->monmax, b->gam};
   for (void *p : bufs)

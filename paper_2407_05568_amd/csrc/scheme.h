@@ -814,6 +814,86 @@ __device__ __forceinline__ void update_point(const Geo &G, const double *__restr
 }
 
 
+// 2D: the direction-0 interface fluxes of a 62 x 4 tile (rows of 64 threads, so that the
+// pair-flux items are one per thread) and the update of the 61 x 4 nodes between them, in one
+// block (the direction-1 fluxes are read from their buffer).  Tiles step by 61 nodes along x,
+// so the tile's last interface is also computed by the next tile; in exchange the direction-0
+// fluxes never go through memory and the separate update kernel is not needed.  The node's
+// sums are those of update_point (direction 0, then direction 1).
+#define FU_TX 62
+#define FU_PX 64
+#define FU_TY 4
+// The tile whose first interface is (bx0, by0), for one 256-thread block; sP: FluxLds<2, 0, FU_TX,
+// FU_TY, 1>::SIZE doubles of LDS.  mode 0: write dJU, dJ; mode 1: the SSP-RK3 stage s combination
+// with dt from dtp; mout (mode 1): also mout = mx + mf dt mxd at the tile's nodes (mout may be mx).
+// ST: the 2D backward-facing step; its solid nodes keep the step's base values (mode 1) or get a
+// zero right-hand side (mode 0).  Every thread reaches the barriers.
+template <bool ST>
+__device__ __forceinline__ void flux_upd2_tile(const Geo &G, const double *__restrict__ nd,
+                                               const double *__restrict__ F1, long nif1, int mode, int s,
+                                               const double *__restrict__ dtp, const double *__restrict__ base_JU,
+                                               const double *__restrict__ base_J, const double *__restrict__ in_JU,
+                                               const double *__restrict__ in_J, double *__restrict__ out_JU,
+                                               double *__restrict__ out_J, unsigned *flags, const double *mx,
+                                               const double *mxd, double mf, double *mout, int bx0, int by0,
+                                               double *__restrict__ sP) {
+  static_assert(FluxLds<2, 0, FU_TX, FU_TY, 1>::SIZE >= 5 * 256, "the interface fluxes reuse the pair-flux LDS");
+  double Fl[5];
+  int a0, a1, a2;
+  const bool ok = flux_tile_eval<2, 0, FU_TX, FU_TY, 1, FU_PX, FU_TY, ST>(G, nd, flags, bx0, by0, 0, sP, Fl, a0, a1, a2);
+  const int tid = threadIdx.x, tx = tid % FU_PX, ty = tid / FU_PX;
+  const int i0 = bx0 + tx, i1 = by0 + ty;
+  const bool upd = tx < FU_TX - 1 && i0 < G.n[0] && i1 < G.n[1];
+  const long t = (long)i1 * G.n[0] + i0;
+  const bool solid = ST && upd && step_solid(G, i0, i1);
+  // the update's operands are loaded before the two barriers below, so that their latency
+  // overlaps the waits (the direction-0 fluxes of the tile are not yet in LDS)
+  double f1l[5], f1h[5], mxv[2], mxdv[2];
+  const double dtm = mout ? *dtp : 0.0;
+  UpdIn<2> u;
+  u.dt = mode == 1 ? *dtp : 0.0;
+  if (upd && !solid) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      f1l[c] = F1[(long)c * nif1 + t];
+      f1h[c] = F1[(long)c * nif1 + t + G.n[0]];
+    }
+    update_load<2>(G, t, mode, s, base_JU, base_J, in_JU, in_J, u);
+  }
+  if (upd && mout) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      mxv[j] = mx[(long)j * G.N + t];
+      mxdv[j] = mxd[(long)j * G.N + t];
+    }
+  }
+  __syncthreads();  // every thread has read its pair fluxes
+  if (ok) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) sP[c * 256 + tid] = Fl[c];
+  }
+  __syncthreads();
+  if (!upd) return;
+  if (mout) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) mout[(long)j * G.N + t] = fma(mf * dtm, mxdv[j], mxv[j]);
+  }
+  if (solid) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) out_JU[(long)c * G.N + t] = mode == 1 ? base_JU[(long)c * G.N + t] : 0.0;
+    out_J[t] = mode == 1 ? base_J[t] : 0.0;
+    return;
+  }
+  double L[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) L[c] = 0.0;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) L[c] += (sP[c * 256 + tid] - sP[c * 256 + tid + 1]) * G.idxi[0];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) L[c] += (f1l[c] - f1h[c]) * G.idxi[1];
+  update_store<2>(G, L, u, t, mode, s, out_JU, out_J, flags);
+}
+
 // =============================== CFL =============================================
 
 // CFL spectral-radius sum at node (i0, i1, i2): sum_k (|v . m_k| + |m_k| c) / (J dxi_k) with
