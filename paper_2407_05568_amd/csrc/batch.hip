@@ -5,7 +5,8 @@
 //   node data of every padded node of every instance
 //   interface fluxes of every instance, both directions
 //   flux differences and the RK combination (+ x^{n+1} = x^n + dt xdot at stage 2)
-// The same phases also run as separate launches (the phased kernels), and the mesh
+// The same phases also run as separate launches (the phased kernels, in which the direction-0
+// fluxes of 62 x 4 tiles are formed together with the update of their nodes), and the mesh
 // redistribution of Section 4 (monitor with per-instance maxima, filter, Jacobi, limiter,
 // mesh velocity) runs batched over the same work lists.  The work items of a phase
 // (interface tiles, or chunks of 256 nodes) are listed instance by instance.  Workgroups are
