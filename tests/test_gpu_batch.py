@@ -122,13 +122,17 @@ def test_batch_step_matches_oracle(orc, torch_dev):
         assert o.flags() == 0
 
 
-def test_batch_moving_mesh_matches_single_path(torch_dev):
+# launch variants: 0 the persistent stage kernel, 5 and 6 the phased launches (the direction-0
+# fluxes fused into the update, with the stage-2 mesh advance)
+@pytest.mark.parametrize("variant", [0, 5, 6])
+def test_batch_moving_mesh_matches_single_path(torch_dev, variant):
     """Stage meshes x + c_s dt xdot and the mesh advance, against rk_stage of the single-problem
     library path on each instance."""
     torch = torch_dev
     from paper_2407_05568_amd.esvdw import Context
     probs = _problems()
     B, off, shapes, x, J, JU = _batch(torch, probs)
+    B.set_variant(variant)
     xs = [synth.smooth_mesh(p, 60 + i, amp=0.02) for i, (p, _) in enumerate(probs)]
     xds = [synth.smooth_velocity(p, 70 + i, amp=0.1) for i, (p, _) in enumerate(probs)]
     x = pack(torch, xs, 2, off)
@@ -292,13 +296,15 @@ def test_batch_redistribute_matches_single_path_and_oracle(orc, torch_dev):
         assert np.abs(nx_g - nx_o).max() <= 1e-13
 
 
-def test_batch_moving_step_matches_single_path(torch_dev):
+@pytest.mark.parametrize("variant", [0, 6])
+def test_batch_moving_step_matches_single_path(torch_dev, variant):
     """A full moving-mesh step of every instance (esvdw_batch_redistribute + esvdw_batch_step)
     against esvdw_step(moving) of the single-problem path, at the conditioning bar."""
     torch = torch_dev
     from paper_2407_05568_amd.esvdw import Context
     probs = _problems()
     B, off, shapes, _, _, _ = _batch(torch, probs)
+    B.set_variant(variant)
     xs, Js, JUs = _moving_setup(torch, probs)
     x, J, JU = pack(torch, xs, 2, off), pack(torch, Js, 1, off), pack(torch, JUs, 4, off)
     xd = torch.zeros_like(x)
